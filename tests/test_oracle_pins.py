@@ -1,0 +1,350 @@
+"""Pins of the FP64 oracle against facts other than itself.
+
+Each test checks the oracle against a closed form, an invariant, a dense linear
+solve, a brute-force sum or a quadrature, chosen so that a plausible mistake in
+the oracle (a dropped term, a wrong sign or index, a transposed axis, a wrong
+normalisation) fails at least one of them.  No GPU is needed.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import dgpe_oracle as O
+import workloads as W
+
+
+def _params(n, d, dt=0.01, trap=(1.0, 1.0, 1.0), g=0.0, gd=0.0, imag=False, R=0.0):
+    return O.Params(n=tuple(n), d=tuple(d), dt=dt, trap=tuple(trap), g=g, gd=gd, imag=imag, R=R)
+
+
+# ---------------------------------------------------------------------------
+# Dipolar kernel and potential
+# ---------------------------------------------------------------------------
+
+def _cutoff_by_quadrature(u):
+    """3 * integral_0^u j2(t)/t dt: the radial part of the Fourier transform of
+    (1 - 3 cos^2)/r^3 restricted to r < R, written through the partial-wave
+    expansion of exp(-i k.r) (a route independent of the closed form)."""
+    val, _ = integrate.quad(lambda t: special.spherical_jn(2, t) / t, 0.0, u, limit=400,
+                            epsabs=1e-15, epsrel=1e-13)
+    return 3.0 * val
+
+
+@pytest.mark.parametrize("u", [0.02, 0.09, 0.11, 0.5, 1.0, math.pi, 7.3, 40.0])
+def test_cutoff_factor_matches_radial_quadrature(u):
+    got = float(O.cutoff_factor(np.array([u]))[0])
+    ref = _cutoff_by_quadrature(u)
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)) + 1e-15
+
+
+def test_cutoff_factor_limits():
+    # F -> u^2/10 for small u, F -> 1 for large u
+    assert abs(float(O.cutoff_factor(np.array([1e-3]))[0]) / 1e-7 - 1.0) < 1e-5
+    assert abs(float(O.cutoff_factor(np.array([1e4]))[0]) - 1.0) < 1e-7
+
+
+def _bruteforce_potential(n, d, R, field):
+    """Circular convolution through an explicit O(N^2) DFT along each axis, with the
+    kernel evaluated on the full (not half) spectrum from the quadrature form."""
+    mats, ks = [], []
+    for a in range(3):
+        m = np.arange(n[a])
+        mats.append(np.exp(-2j * np.pi * np.outer(m, m) / n[a]))
+        signed = np.where(m <= n[a] // 2, m, m - n[a])
+        ks.append(2 * np.pi * signed / (n[a] * d[a]))
+    spec = np.einsum("ai,bj,ck,ijk->abc", mats[0], mats[1], mats[2], field)
+    U = np.zeros(n)
+    for i in range(n[0]):
+        for j in range(n[1]):
+            for l in range(n[2]):
+                k2 = ks[0][i] ** 2 + ks[1][j] ** 2 + ks[2][l] ** 2
+                if k2 == 0:
+                    continue
+                ang = 3.0 * ks[2][l] ** 2 / k2 - 1.0
+                U[i, j, l] = 4 * np.pi / 3 * ang * _cutoff_by_quadrature(math.sqrt(k2) * R)
+    back = np.einsum("ai,bj,ck,ijk->abc", mats[0].conj(), mats[1].conj(), mats[2].conj(), U * spec)
+    return (back / field.size).real
+
+
+@pytest.mark.parametrize("n", [(4, 6, 8), (6, 4, 5)])
+def test_potential_matches_bruteforce_dft(n):
+    d = (0.7, 0.5, 0.4)
+    R = 1.1
+    rng = np.random.default_rng(11)
+    field = rng.uniform(0.0, 1.0, size=n)
+    p = _params(n, d, R=R, gd=1.0)
+    got = O.dipolar_potential(p, field)
+    ref = _bruteforce_potential(n, d, R, field)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_isotropic_density_has_zero_dipolar_energy():
+    # A spherically symmetric density on a cubic grid: the angular factor
+    # 3 kz^2/k^2 - 1 averages to zero over the x<->y<->z permutations of k.
+    n, d = (32, 32, 32), (0.4, 0.4, 0.4)
+    p = _params(n, d, gd=1.0)
+    psi = W.gaussian_state(n, d, (1.0, 1.0, 1.0))
+    dens = np.abs(psi) ** 2
+    edd = 0.5 * np.sum(O.dipolar_potential(p, dens) * dens) * p.dV
+    assert abs(edd) < 1e-15
+
+
+def _edd_gaussian_closed(sr, sz):
+    """Dipolar energy (gd = 1, no cut-off) of the unit-norm density
+    exp(-rho^2/sr^2 - z^2/sz^2)/(pi^1.5 sr^2 sz): by Parseval,
+    E = 1/2 (2 pi)^-3 int (4 pi/3)(3 cos^2 a - 1) |n~(k)|^2 d^3k with
+    |n~|^2 = exp(-k^2 (sr^2 sin^2 a + sz^2 cos^2 a)/2); the radial integral is
+    sqrt(pi/2) s^-3 and the angular one is done by quadrature."""
+    ang, _ = integrate.quad(lambda u: (3 * u * u - 1) / (sr ** 2 + (sz ** 2 - sr ** 2) * u * u) ** 1.5,
+                            -1.0, 1.0, epsabs=1e-15, epsrel=1e-13)
+    return 0.5 * (2 * np.pi) ** -3 * (4 * np.pi / 3) * (2 * np.pi) * math.sqrt(np.pi / 2) * ang
+
+
+def _edd_gaussian_kappa(sr, sz):
+    """The same energy through the elementary closed form in kappa = sr/sz:
+    E = -f(kappa) / (3 sqrt(2 pi) sr^2 sz), f = (1 + 2k^2)/(1 - k^2)
+    - 3 k^2 artanh(sqrt(1 - k^2))/(1 - k^2)^1.5 (analytic continuation for k > 1)."""
+    k = sr / sz
+    if k < 1:
+        s = math.sqrt(1 - k * k)
+        f = (1 + 2 * k * k) / (1 - k * k) - 3 * k * k * math.atanh(s) / (1 - k * k) ** 1.5
+    else:
+        s = math.sqrt(k * k - 1)
+        f = (1 + 2 * k * k) / (1 - k * k) - 3 * k * k * math.atan(s) / ((1 - k * k) * s)
+    return -f / (3 * math.sqrt(2 * np.pi) * sr * sr * sz)
+
+
+@pytest.mark.parametrize("sr,sz", [(1.0, 0.6), (1.0, 1.6), (0.8, 2.0), (1.5, 0.5)])
+def test_dipolar_energy_of_anisotropic_gaussian(sr, sz):
+    closed = _edd_gaussian_closed(sr, sz)
+    assert abs(_edd_gaussian_kappa(sr, sz) - closed) < 1e-12 * abs(closed)
+    # box L = 32 and cut-off R = 16: both the cut-off and the periodic images are
+    # far outside the density's autocorrelation, so the grid value must reach the
+    # uncut closed form to near rounding
+    n, d = (128, 128, 256), (0.25, 0.25, 0.125)
+    p = _params(n, d, gd=1.0)
+    x, y, z = O.grid(p)
+    rho2 = (x ** 2)[:, None, None] + (y ** 2)[None, :, None]
+    dens = np.exp(-rho2 / sr ** 2 - (z ** 2)[None, None, :] / sz ** 2) / (np.pi ** 1.5 * sr * sr * sz)
+    psi = np.sqrt(dens).astype(np.complex128)
+    edd = O.observables(p, psi)["e_dd"]
+    assert abs(edd - closed) < 1e-11 * abs(closed)
+
+
+# ---------------------------------------------------------------------------
+# Crank-Nicolson sweeps
+# ---------------------------------------------------------------------------
+
+def _dense_cn(u, A, axis):
+    N = u.shape[axis]
+    D = -2 * np.eye(N) + np.eye(N, k=1) + np.eye(N, k=-1)
+    lhs = np.eye(N) - A * D
+    rhs_op = np.eye(N) + A * D
+    v = np.moveaxis(u, axis, 0).reshape(N, -1)
+    out = np.linalg.solve(lhs, rhs_op @ v)
+    return np.moveaxis(out.reshape(np.moveaxis(u, axis, 0).shape), 0, axis)
+
+
+@pytest.mark.parametrize("imag", [False, True])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_cn_sweep_matches_dense_solve(imag, axis):
+    n, d = (5, 6, 7), (0.3, 0.2, 0.25)
+    p = _params(n, d, dt=0.03, imag=imag)
+    rng = np.random.default_rng(3 + axis)
+    u = rng.normal(size=n) + 1j * rng.normal(size=n)
+    A = O.cn_coefficient(p, axis)
+    assert (A.imag == 0) == imag
+    assert abs(abs(A) - 0.03 / (4 * d[axis] ** 2)) < 1e-15
+    got = O.cn_solve_axis(u, A, axis)
+    ref = _dense_cn(u, A, axis)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_cn_real_time_is_unitary_and_commutes():
+    n, d = (9, 10, 11), (0.2, 0.25, 0.3)
+    p = _params(n, d, dt=0.05)
+    psi = W.random_state(n, d, seed=5)
+    out = O.kinetic_step(p, psi)
+    assert abs(O.norm(p, out) - O.norm(p, psi)) < 1e-14
+    ax = [O.cn_coefficient(p, a) for a in range(3)]
+    zyx = O.cn_solve_axis(O.cn_solve_axis(O.cn_solve_axis(psi, ax[2], 2), ax[1], 1), ax[0], 0)
+    assert np.max(np.abs(zyx - out)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Whole steps
+# ---------------------------------------------------------------------------
+
+def _axis_transfer(p, axis, a=1.0):
+    """Dense one-axis transfer matrix C_axis diag(exp(-i dt a V_axis)) (real time) or
+    C_axis diag(exp(-dt a V_axis)) (imaginary time), V_axis = trap^2 x^2 / 2."""
+    N = p.n[axis]
+    x = (np.arange(N) - N // 2) * p.d[axis]
+    v = 0.5 * (p.trap[axis] * x) ** 2
+    phase = np.exp(-p.dt * a * v) if p.imag else np.exp(-1j * p.dt * a * v)
+    A = p.dt / (4 * p.d[axis] ** 2) * (1.0 if p.imag else 1j)
+    D = -2 * np.eye(N) + np.eye(N, k=1) + np.eye(N, k=-1)
+    C = np.linalg.solve(np.eye(N) - A * D, np.eye(N) + A * D)
+    return C @ np.diag(phase)
+
+
+@pytest.mark.parametrize("imag", [False, True])
+def test_noninteracting_step_is_exactly_separable(imag):
+    n, d = (10, 12, 14), (0.4, 0.3, 0.35)
+    p = _params(n, d, dt=0.02, trap=(1.0, 1.3, 2.1), imag=imag)
+    rng = np.random.default_rng(7)
+    f = [rng.normal(size=n[a]) + 1j * rng.normal(size=n[a]) for a in range(3)]
+    psi0 = np.einsum("i,j,k->ijk", *f)
+    steps = 15
+    got = O.evolve(p, psi0, steps)
+    g = [np.linalg.matrix_power(_axis_transfer(p, a), steps) @ f[a] for a in range(3)]
+    ref = np.einsum("i,j,k->ijk", *g)
+    if imag:
+        ref = ref / math.sqrt(np.sum(np.abs(ref) ** 2) * p.dV)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_noninteracting_ground_state_energy():
+    # Imaginary-time fixed point of the non-interacting step: the product of the
+    # dominant eigenvectors of the one-axis transfer matrices.  Its energy tends to
+    # (nu + lam + gam)/2 with O(dx^2) + O(dt) error.
+    trap = (1.0, 1.5, 2.0)
+    errs = []
+    for h, dt in [(0.2, 0.004), (0.1, 0.001)]:
+        n = (int(round(12 / h)),) * 3
+        p = _params(n, (h, h, h), dt=dt, trap=trap, imag=True)
+        vecs = []
+        for a in range(3):
+            w, v = np.linalg.eig(_axis_transfer(p, a))
+            vecs.append(v[:, np.argmax(np.abs(w))])
+        psi = np.einsum("i,j,k->ijk", *vecs)
+        psi = psi / math.sqrt(O.norm(p, psi))
+        # the fixed point is invariant under one more oracle step
+        assert np.max(np.abs(np.abs(O.step(p, psi)) - np.abs(psi))) < 1e-10 * np.max(np.abs(psi))
+        obs = O.observables(p, psi)
+        errs.append(abs(obs["energy"] - sum(trap) / 2))
+        for a in range(3):
+            assert abs(obs["rms"][a] - 1 / math.sqrt(2 * trap[a])) < 5 * h * h
+    assert errs[0] < 1.5e-2 and errs[1] < 4e-3 and errs[1] < errs[0] / 3
+
+
+def test_gaussian_observables_closed_forms():
+    trap = (1.0, 1.4, 0.7)
+    n, d = (64, 64, 80), (0.2, 0.2, 0.25)
+    p = _params(n, d, trap=trap)
+    psi = W.gaussian_state(n, d, trap)
+    o = O.observables(p, psi)
+    assert abs(o["norm"] - 1) < 1e-12
+    assert abs(o["e_trap"] - sum(trap) / 4) < 1e-10
+    # the 3-point kinetic energy of a Gaussian is (nu+lam+gam)/4 up to O(d^2)
+    exact_kin = sum(trap) / 4
+    assert abs(o["e_kin"] - exact_kin) < 0.02 * exact_kin
+    for a in range(3):
+        assert abs(o["rms"][a] - 1 / math.sqrt(2 * trap[a])) < 1e-10
+    assert abs(o["rms"][3] - math.sqrt(sum(1 / (2 * t) for t in trap))) < 1e-10
+
+
+def test_real_time_conserves_norm_and_reverses():
+    n, d = (16, 16, 20), (0.35, 0.35, 0.3)
+    p = _params(n, d, dt=0.004, trap=(1.0, 1.0, 2.0), g=30.0, gd=12.0)
+    psi0 = W.random_state(n, d, seed=9)
+    psi = O.evolve(p, psi0, 25)
+    assert abs(O.norm(p, psi) - 1.0) < 1e-13
+    # The inverse step: Crank-Nicolson with -dt, then the phase with -dt, which
+    # sees the same density because the phase preserves |psi|.
+    back = _params(n, d, dt=-0.004, trap=(1.0, 1.0, 2.0), g=30.0, gd=12.0)
+    for _ in range(25):
+        psi = O.nonlinear_step(back, O.kinetic_step(back, psi))
+    assert np.max(np.abs(psi - psi0)) < 1e-12 * np.max(np.abs(psi0))
+
+
+def test_real_time_energy_drift_is_first_order_in_dt():
+    # With consistent signs of the kinetic, trap and interaction parts the split
+    # step conserves the energy up to the splitting error, which shrinks with dt.
+    n, d = (20, 20, 20), (0.4, 0.4, 0.4)
+    cfg = W.Config("t", n, d, 0.0, (1.0, 1.0, 1.5), 25.0, 10.0, True, 0)
+    psi0 = W.gaussian_state(n, d, (0.8, 0.8, 1.0))
+    drifts = []
+    for dt in (0.004, 0.002):
+        p = O.Params.from_config(cfg, dt=dt, imag=False)
+        e0 = O.observables(p, psi0)["energy"]
+        psi = O.evolve(p, psi0, int(round(0.2 / dt)))
+        drifts.append(abs(O.observables(p, psi)["energy"] - e0))
+    assert drifts[0] < 2e-3
+    assert drifts[1] < 0.7 * drifts[0]
+
+
+def test_interacting_ground_state_virial_and_eigen_residual():
+    # For the ground state of the dipolar GPE, 2 E_kin - 2 E_trap + 3 E_c + 3 E_dd = 0
+    # (dilation of the state), and H psi = mu psi.
+    n, d = (24, 24, 24), (0.45, 0.45, 0.45)
+    p = _params(n, d, dt=0.002, trap=(1.0, 1.0, 1.4), g=20.0, gd=8.0, imag=True)
+    psi = W.gaussian_state(n, d, p.trap)
+    psi = O.evolve(p, psi, 1500)
+    o = O.observables(p, psi)
+    scale = o["e_kin"] + o["e_trap"] + o["e_contact"] + abs(o["e_dd"])
+    vir = 2 * o["e_kin"] - 2 * o["e_trap"] + 3 * o["e_contact"] + 3 * o["e_dd"]
+    assert abs(vir) < 0.02 * scale
+    res = O.hamiltonian_apply(p, psi) - o["mu"] * psi
+    assert np.linalg.norm(res) < 0.02 * o["mu"] * np.linalg.norm(psi)
+    assert o["e_dd"] < 0  # elongated along the dipoles (gam < lam): attractive
+
+
+# ---------------------------------------------------------------------------
+# Adjoint
+# ---------------------------------------------------------------------------
+
+def _small_real_params():
+    n, d = (8, 10, 12), (0.5, 0.45, 0.4)
+    return _params(n, d, dt=0.01, trap=(1.0, 1.2, 1.7), g=15.0, gd=9.0, imag=False)
+
+
+def _forward_J(p, psi0, amp, objective="energy", target=None):
+    psi = O.evolve(p, psi0, len(amp) - 1, amp)
+    if objective == "energy":
+        return O.energy_total(p, psi, amp[-1])
+    return O.overlap_objective(p, psi, target)[0]
+
+
+@pytest.mark.parametrize("objective", ["energy", "overlap"])
+def test_adjoint_matches_central_differences(objective):
+    p = _small_real_params()
+    psi0 = W.random_state(p.n, p.d, seed=21)
+    target = W.random_state(p.n, p.d, seed=22) if objective == "overlap" else None
+    amp = np.random.default_rng(23).uniform(0.8, 1.2, size=7)
+    J, psiN, dJ_da, dJ_dtrap, lam0 = O.adjoint_evolve(p, psi0, amp, objective, target)
+    assert abs(J - _forward_J(p, psi0, amp, objective, target)) < 1e-14 * abs(J)
+    h = 1e-4
+    fd = np.zeros(len(amp))
+    for i in range(len(amp)):
+        ap, am = amp.copy(), amp.copy()
+        ap[i] += h
+        am[i] -= h
+        fd[i] = (_forward_J(p, psi0, ap, objective, target) - _forward_J(p, psi0, am, objective, target)) / (2 * h)
+    scale = max(np.max(np.abs(fd)), 1e-3 * abs(J))
+    assert np.max(np.abs(dJ_da - fd)) < 1e-6 * scale
+    for j in range(3):
+        tp, tm = list(p.trap), list(p.trap)
+        tp[j] += h
+        tm[j] -= h
+        pp = O.Params(p.n, p.d, p.dt, tuple(tp), p.g, p.gd, p.imag, p.R)
+        pm = O.Params(p.n, p.d, p.dt, tuple(tm), p.g, p.gd, p.imag, p.R)
+        fdj = (_forward_J(pp, psi0, amp, objective, target) - _forward_J(pm, psi0, amp, objective, target)) / (2 * h)
+        assert abs(dJ_dtrap[j] - fdj) < 1e-6 * max(abs(fdj), 1e-3 * abs(J))
+    v = W.random_state(p.n, p.d, seed=24)
+    fdv = (_forward_J(p, psi0 + h * v, amp, objective, target)
+           - _forward_J(p, psi0 - h * v, amp, objective, target)) / (2 * h)
+    adj = float(np.real(np.sum(np.conj(lam0) * v)))
+    assert abs(adj - fdv) < 1e-6 * max(abs(fdv), 1e-3 * abs(J))
+
+
+def test_adjoint_sweep_is_conjugate_transpose():
+    # <lam, C u> = <C^H lam, u> with C^H the sweep with conj(A)
+    p = _small_real_params()
+    u = W.random_state(p.n, p.d, seed=31)
+    lam = W.random_state(p.n, p.d, seed=32)
+    lhs = np.vdot(lam, O.kinetic_step(p, u))
+    rhs = np.vdot(O.kinetic_step(p, lam, conjugate=True), u)
+    assert abs(lhs - rhs) < 1e-14 * abs(lhs) + 1e-16
