@@ -1,0 +1,177 @@
+/*
+ * dgpe.h -- C ABI of libdgpe, the MI355X (gfx950) split-step Crank-Nicolson
+ * time step of the three-dimensional dipolar Gross-Pitaevskii equation (GPE).
+ *
+ * Method (paper, program summary, "Nature of problem" and "Solution method";
+ * "Summary of revisions" for the real-to-complex transform of the density):
+ * the GPE with contact and dipolar interaction in an anisotropic harmonic trap,
+ * discretised in space and time and propagated over small steps in imaginary
+ * time (ground state) or real time (dynamics); the dipolar term is evaluated in
+ * momentum space through the convolution theorem.  In trap units:
+ *
+ *   real time       i dpsi/dt  =  [-1/2 Lap + V + g|psi|^2 + gd Phi] psi
+ *   imaginary time    dpsi/dtau = -[...] psi
+ *   V   = a(t)/2 (nu^2 x^2 + lam^2 y^2 + gam^2 z^2)
+ *   Phi = IDFT[ U_R(k) DFT[|psi|^2] ],  dipoles along z,
+ *   U_R = (4 pi/3)(3 kz^2/k^2 - 1)(1 + 3 cos(kR)/(kR)^2 - 3 sin(kR)/(kR)^3), U_R(0) = 0.
+ *
+ * One step: theta = dt (V + g n + gd Phi[n]) from the pre-step density n;
+ * psi <- psi exp(-i theta) (real) or psi exp(-theta) (imaginary); then the
+ * Crank-Nicolson solve (1 - A D) psi' = (1 + A D) psi along x, y and z with
+ * D = [1, -2, 1], zero ghost values, A = i dt/(4 d^2) (real) or dt/(4 d^2)
+ * (imaginary); in imaginary time psi is then rescaled to sum |psi|^2 dV = 1.
+ * Grid: x_i = (i - Nx/2) dx (likewise y, z).
+ *
+ * Layout: every grid array is C-ordered [Nx][Ny][Nz] with z contiguous and x
+ * slowest (paper, DBEC-GP-MPI package, data distribution along NX).  Complex
+ * values are interleaved (re, im): complex128 for DGPE_F64 plans, complex64
+ * for DGPE_F32 plans.  Real arrays (Phi) have the plan's real type.
+ *
+ * Ownership: the caller allocates every device buffer (state, workspace,
+ * adjoint workspace) and keeps it alive while the plan or call uses it; the
+ * library allocates no device memory.  The plan owns only host metadata.
+ * Device pointers must be 256-byte aligned.
+ *
+ * Streams: all work is enqueued on the plan's HIP stream.  dgpe_step and
+ * dgpe_potential are asynchronous and report only argument and launch errors;
+ * dgpe_energy_mu_rms and dgpe_step_adjoint synchronise the stream and report
+ * deferred errors.  A plan is not re-entrant; distinct plans are independent.
+ *
+ * Errors: every call returns a dgpe_status; dgpe_last_error() gives a
+ * thread-local message for the last failure.  Grid sizes must be even, have no
+ * prime factor other than 2 and 3 (the paper's FFT-friendly sizes restricted to
+ * the radices implemented here) and lie in [4, 1024]; invalid arguments are
+ * rejected before any work is enqueued (the library's counterpart of the
+ * paper's input checks, "Additional comments").
+ */
+#ifndef DGPE_H
+#define DGPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dgpe_plan_s* dgpe_plan;
+
+typedef enum {
+    DGPE_OK = 0,
+    DGPE_EINVAL = 1,             /* an argument is out of range or inconsistent   */
+    DGPE_EUNSUPPORTED_SIZE = 2,  /* a grid size has a factor other than 2 and 3  */
+    DGPE_EWORKSPACE = 3,         /* workspace missing, misaligned or too small   */
+    DGPE_EHIP = 4,               /* the HIP runtime reported an error            */
+    DGPE_ENONFINITE = 5,         /* a reduction met NaN or Inf                   */
+    DGPE_ESTATE = 6              /* the call does not fit the plan's mode        */
+} dgpe_status;
+
+/* mode = time | precision */
+#define DGPE_IMAG 0u
+#define DGPE_REAL 1u
+#define DGPE_F64 0u
+#define DGPE_F32 2u
+
+/* dgpe_plan_set parameters */
+#define DGPE_PARAM_G 0
+#define DGPE_PARAM_GD 1
+#define DGPE_PARAM_TRAP_NU 2
+#define DGPE_PARAM_TRAP_LAMBDA 3
+#define DGPE_PARAM_TRAP_GAMMA 4
+#define DGPE_PARAM_DT 5
+#define DGPE_PARAM_REAL_TIME 6 /* value 1: real time, 0: imaginary time */
+
+/* adjoint objectives */
+#define DGPE_OBJ_ENERGY 0
+#define DGPE_OBJ_OVERLAP 1
+
+/* Observables (paper: the programs report the chemical potential, energy and
+ * rms sizes of the state).  Sums are FP64 over the grid times dV:
+ *   e_kin  = 1/2 sum_axes sum_{i=-1}^{N-1} |psi_{i+1} - psi_i|^2 / d^2 (ghost zeros)
+ *   e_trap = sum a V0 |psi|^2,  e_contact = g/2 sum |psi|^4,  e_dd = gd/2 sum Phi |psi|^2
+ *   energy = (e_kin + e_trap + e_contact + e_dd)/norm
+ *   mu     = (e_kin + e_trap + 2 e_contact + 2 e_dd)/norm
+ *   rms    = sqrt(<x^2>), sqrt(<y^2>), sqrt(<z^2>), sqrt(<r^2>) about the origin. */
+typedef struct {
+    double norm, mu, energy, e_kin, e_trap, e_contact, e_dd;
+    double rms[4];
+} dgpe_obs;
+
+/* Bytes of device workspace a plan of grid n[3] and mode needs (0 if the
+ * arguments are invalid). */
+size_t dgpe_workspace_bytes(const int32_t n[3], uint32_t mode);
+
+/* Create a plan.
+ *   n[3]        Nx, Ny, Nz (each even, 2^a 3^b, 4..1024)
+ *   d[3]        grid spacings > 0
+ *   dt          time step > 0
+ *   trap[3]     nu, lambda, gamma (trap frequencies along x, y, z), finite
+ *   g, gd       contact and dipolar strengths, finite
+ *   cutoff_R    kernel cut-off radius; <= 0 selects min(N_i d_i)/2
+ *   mode        DGPE_IMAG | DGPE_REAL, combined with DGPE_F64 | DGPE_F32
+ *   workspace   device buffer of workspace_bytes >= dgpe_workspace_bytes()
+ *   hip_stream  hipStream_t for all work (NULL: the default stream)
+ * Fills the workspace's constant tables (dipolar kernel, twiddles, Thomas
+ * factors) and synchronises the stream once.  On failure *out is NULL. */
+dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[3], double dt,
+                             const double trap[3], double g, double gd, double cutoff_R,
+                             uint32_t mode, void* workspace, size_t workspace_bytes,
+                             void* hip_stream);
+
+/* Change one physical parameter (DGPE_PARAM_*).  DT and REAL_TIME rebuild the
+ * Thomas tables (synchronous); the others take effect at the next launch. */
+dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value);
+
+/* Redirect subsequent work to another HIP stream. */
+dgpe_status dgpe_plan_set_stream(dgpe_plan plan, void* hip_stream);
+
+/* Advance psi (device, [Nx][Ny][Nz] complex of the plan precision, in place) by
+ * nsteps split steps.  amp: host array of nsteps trap amplitudes a(t_n) (NULL:
+ * all 1); it is read during the call only.  In imaginary time the returned
+ * state has unit norm.  Asynchronous. */
+dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp);
+
+/* Dipolar potential Phi = IDFT[U_R DFT[|psi|^2]] of a state (paper, "Solution
+ * method": the dipolar term through the convolution theorem).  phi: device
+ * [Nx][Ny][Nz] real of the plan precision.  Asynchronous. */
+dgpe_status dgpe_potential(dgpe_plan plan, const void* psi, void* phi);
+
+/* Norm, chemical potential, energy and its parts, rms sizes of psi with trap
+ * amplitude amp.  Synchronises the stream; DGPE_ENONFINITE if any sum is not
+ * finite. */
+dgpe_status dgpe_energy_mu_rms(dgpe_plan plan, const void* psi, double amp, dgpe_obs* out);
+
+/* Bytes of adjoint workspace for dgpe_step_adjoint(nsteps, ckpt_every). */
+size_t dgpe_adjoint_workspace_bytes(dgpe_plan plan, int32_t nsteps, int32_t ckpt_every);
+
+/* Reverse-mode gradient of a final-state objective through nsteps real-time
+ * steps from psi0 (the hand-written adjoint of the split step; its equations
+ * are the transpose of the forward step's linearisation):
+ *   amp       host, nsteps+1 amplitudes: a(t_n) for step n, amp[nsteps] = a(T)
+ *   objective DGPE_OBJ_ENERGY: J = e_kin + e_trap + e_contact + e_dd of psi_N
+ *             (not divided by the norm, which real time conserves), trap
+ *             amplitude amp[nsteps];
+ *             DGPE_OBJ_OVERLAP: J = |sum conj(target) psi_N dV|^2 (target:
+ *             device state of the plan precision).
+ *   adj_ws    device buffer of >= dgpe_adjoint_workspace_bytes(); holds the
+ *             checkpoints (every ckpt_every steps, recomputed per segment).
+ * Outputs (host unless stated): J; dJ_damp[nsteps+1]; dJ_dtrap[3] for
+ * (nu, lambda, gamma); psi_final (device, nullable) = psi_N; dJ_dpsi0 (device,
+ * nullable) = the cotangent lam_0 with dJ = Re sum conj(lam_0) dpsi0.
+ * Real-time plans only (DGPE_ESTATE otherwise).  Synchronises the stream. */
+dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, const double* amp,
+                              int32_t ckpt_every, int32_t objective, const void* target,
+                              void* adj_ws, size_t adj_ws_bytes, void* psi_final, double* J,
+                              double* dJ_damp, double dJ_dtrap[3], void* dJ_dpsi0);
+
+/* Release the plan's host metadata (the workspace stays with the caller). */
+void dgpe_plan_destroy(dgpe_plan plan);
+
+const char* dgpe_status_string(dgpe_status status);
+const char* dgpe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGPE_H */

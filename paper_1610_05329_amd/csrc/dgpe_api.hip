@@ -1,0 +1,679 @@
+// libdgpe C ABI: plan creation (validation, constant tables, launch shapes),
+// the split-step time loop, the dipolar potential, the observables and the
+// checkpointed adjoint.  All device memory belongs to the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dgpe.h"
+#include "dgpe_internal.h"
+
+using namespace dgpe;
+
+// The opaque handle of the C ABI is the plan itself.
+struct dgpe_plan_s : public dgpe::Plan {};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dgpe_status fail(dgpe_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define DGPE_HIP(expr)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(DGPE_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kThreads = 256;
+constexpr int kEmax = 16;
+constexpr size_t kLdsBudget = 64 * 1024;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+bool size_ok(int n) {
+    if (n < 4 || n > 1024 || (n & 1)) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+FftDesc factor(int L) {
+    FftDesc f{};
+    f.L = L;
+    int r = L;
+    std::vector<int> rad;
+    while (r % 8 == 0) { rad.push_back(8); r /= 8; }
+    if (r % 4 == 0) { rad.push_back(4); r /= 4; }
+    if (r % 2 == 0) { rad.push_back(2); r /= 2; }
+    while (r % 3 == 0) { rad.push_back(3); r /= 3; }
+    f.nstages = (int)rad.size();
+    for (int i = 0; i < f.nstages; ++i) f.radix[i] = rad[i];
+    return f;
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << (l + 1)) <= v) ++l;
+    return l;
+}
+
+size_t c2r_step_lds(int Nz, int B, size_t csz) {
+    const int M = Nz / 2, es = B + 1;
+    return (size_t)((M + 1) * es + Nz * es + M + M + 1) * csz;
+}
+
+// Block shapes for a grid; false if no shape fits the LDS budget.
+bool choose_launch(const int n[3], bool f32, Launch* lc) {
+    const size_t csz = f32 ? 8 : 16;
+    lc->threads = kThreads;
+    const int cap = kEmax * kThreads;
+    const int Nx = n[0], Ny = n[1], Nz = n[2];
+    const int M = Nz / 2;
+    // z passes: B lines, B | Ny, B*M <= cap, LDS within budget
+    int Bz = f32 ? 16 : 8;
+    while (Bz > 1 && (Ny % Bz || Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsBudget)) Bz >>= 1;
+    if (Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsBudget) return false;
+    lc->logB_z = ilog2(Bz);
+    // z segments: B * nseg <= threads
+    int sz = 16;
+    while (sz < 32 && Bz * ((Nz + sz - 1) / sz) > kThreads) sz <<= 1;
+    if (Bz * ((Nz + sz - 1) / sz) > kThreads) return false;
+    if (2 * ((Nz + sz - 1) / sz) * Bz > (M + 1) * (Bz + 1)) return false;
+    lc->seg[2] = sz;
+    // y rows
+    int By = f32 ? 16 : 8;
+    while (By > 1 && (By * Ny > cap || (size_t)(Ny * (By + 1) + Ny) * csz > kLdsBudget)) By >>= 1;
+    if ((size_t)(Ny * (By + 1) + Ny) * csz > kLdsBudget || By * Ny > cap) return false;
+    lc->logB_y = ilog2(By);
+    // x columns: B | Ny
+    int Bx = f32 ? 16 : 8;
+    while (Bx > 1 && (Ny % Bx || Bx * Nx > cap || (size_t)(Nx * (Bx + 1) + Nx) * csz > kLdsBudget))
+        Bx >>= 1;
+    if (Bx * Nx > cap || (size_t)(Nx * (Bx + 1) + Nx) * csz > kLdsBudget) return false;
+    lc->logB_x = ilog2(Bx);
+    // strided sweeps: columns C, segments S, ZB | C, nseg * ZB <= 1024
+    for (int axis = 0; axis < 2; ++axis) {
+        const int L = n[axis];
+        const int C = axis == 1 ? Nz : Ny * Nz;
+        bool ok = false;
+        const int segs[2] = {16, 32};
+        for (int si = 0; si < 2 && !ok; ++si) {
+            const int S = segs[si];
+            if (!f32 && S == 32 && L <= 512) continue;  // keep FP64 register use low
+            const int nseg = (L + S - 1) / S;
+            for (int zb = 64; zb >= 1; zb >>= 1) {
+                if (C % zb == 0 && nseg * zb <= 1024 && (zb >= 16 || zb == C)) {
+                    lc->seg[axis] = S;
+                    lc->logZB[axis] = ilog2(zb);
+                    ok = true;
+                    break;
+                }
+            }
+        }
+        if (!ok) {
+            // small grids: any power-of-two column block
+            const int S = 16, nseg = (L + S - 1) / S;
+            for (int zb = 64; zb >= 1 && !ok; zb >>= 1)
+                if (C % zb == 0 && nseg * zb <= 1024) {
+                    lc->seg[axis] = S;
+                    lc->logZB[axis] = ilog2(zb);
+                    ok = true;
+                }
+        }
+        if (!ok) return false;
+    }
+    return true;
+}
+
+enum {
+    OFF_SPEC, OFF_PHI, OFF_UK, OFF_TWX, OFF_TWY, OFF_TWZ, OFF_TWR, OFF_CN0, /* 6 tables */
+    OFF_RED = OFF_CN0 + 6, OFF_SCAL, OFF_END
+};
+
+size_t red_count_for(const int n[3], const Launch& lc) {
+    const size_t nx = n[0], ny = n[1], nz = n[2];
+    size_t r = 10 * 2048;
+    r = std::max(r, ny * nz);                       // x-sweep blocks (>= 1 column each)
+    r = std::max(r, nx * nz);                       // y-sweep blocks
+    r = std::max(r, 4 * nx * (ny >> lc.logB_z));    // adjoint r2c partials
+    return r;
+}
+
+// Computes the workspace carve-up; offs[OFF_END] is the total.
+bool layout(const int n[3], bool f32, size_t offs[OFF_END + 1], Launch* lc_out) {
+    Launch lc;
+    if (!choose_launch(n, f32, &lc)) return false;
+    if (lc_out) *lc_out = lc;
+    const size_t csz = f32 ? 8 : 16, rsz = f32 ? 4 : 8;
+    const size_t nx = n[0], ny = n[1], nz = n[2];
+    size_t sz[OFF_END];
+    sz[OFF_SPEC] = (nz / 2 + 1) * nx * ny * csz;
+    sz[OFF_PHI] = nx * ny * nz * rsz;
+    sz[OFF_UK] = (nz / 2 + 1) * (nx / 2 + 1) * (ny / 2 + 1) * rsz;
+    sz[OFF_TWX] = nx * csz;
+    sz[OFF_TWY] = ny * csz;
+    sz[OFF_TWZ] = (nz / 2) * csz;
+    sz[OFF_TWR] = (nz / 2 + 1) * csz;
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 2; ++c) sz[OFF_CN0 + 2 * a + c] = TAB_COUNT * (size_t)n[a] * csz;
+    sz[OFF_RED] = red_count_for(n, lc) * sizeof(double);
+    sz[OFF_SCAL] = 16 * sizeof(double);
+    size_t o = 0;
+    for (int i = 0; i < OFF_END; ++i) {
+        offs[i] = o;
+        o += align_up(sz[i]);
+    }
+    offs[OFF_END] = o;
+    return true;
+}
+
+// W_L^m = exp(-2 pi i m / L) in extended precision, rounded once.
+template <typename T>
+std::vector<T> twiddles(int L, int count) {
+    std::vector<T> out(2 * (size_t)count);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int m = 0; m < count; ++m) {
+        const long double a = -2.0L * pi * (long double)m / (long double)L;
+        out[2 * m] = (T)cosl(a);
+        out[2 * m + 1] = (T)sinl(a);
+    }
+    return out;
+}
+
+// Thomas factors of tridiag(-A, 1 + 2A, -A) and the segment carry products.
+template <typename T>
+std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
+    using C = std::complex<long double>;
+    std::vector<C> m(N), al(N), ga(N), P(N), Q(N);
+    const C sub = -A, diag = C(1) + C(2) * A, sup = -A;
+    C cprev = 0;
+    for (int i = 0; i < N; ++i) {
+        m[i] = C(1) / (diag - sub * cprev);
+        const C cp = sup * m[i];
+        al[i] = -sub * m[i];
+        ga[i] = -cp;
+        cprev = cp;
+    }
+    for (int s0 = 0; s0 < N; s0 += S) {
+        const int s1 = std::min(s0 + S, N);
+        C acc = 1;
+        for (int i = s0; i < s1; ++i) { acc *= al[i]; P[i] = acc; }
+        acc = 1;
+        for (int i = s1 - 1; i >= s0; --i) { acc *= ga[i]; Q[i] = acc; }
+    }
+    std::vector<T> out(2 * TAB_COUNT * (size_t)N);
+    const std::vector<C>* tabs[TAB_COUNT];
+    tabs[TAB_M] = &m;
+    tabs[TAB_ALPHA] = &al;
+    tabs[TAB_GAMMA] = &ga;
+    tabs[TAB_P] = &P;
+    tabs[TAB_Q] = &Q;
+    for (int t = 0; t < TAB_COUNT; ++t)
+        for (int i = 0; i < N; ++i) {
+            out[2 * ((size_t)t * N + i)] = (T)(*tabs[t])[i].real();
+            out[2 * ((size_t)t * N + i) + 1] = (T)(*tabs[t])[i].imag();
+        }
+    return out;
+}
+
+template <typename T>
+dgpe_status upload(void* dst, const std::vector<T>& v) {
+    DGPE_HIP(hipMemcpy(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return DGPE_OK;
+}
+
+template <typename T>
+dgpe_status build_cn_tables(Plan& p) {
+    for (int a = 0; a < 3; ++a) {
+        const long double c = (long double)p.dt / (4.0L * (long double)p.d[a] * (long double)p.d[a]);
+        for (int cj = 0; cj < 2; ++cj) {
+            std::complex<long double> A = p.imag ? std::complex<long double>(c, 0)
+                                                 : std::complex<long double>(0, cj ? -c : c);
+            dgpe_status s = upload(p.cntab[a][cj], cn_tables<T>(p.n[a], A, p.lc.seg[a]));
+            if (s != DGPE_OK) return s;
+        }
+    }
+    return DGPE_OK;
+}
+
+template <typename T>
+dgpe_status build_tables(Plan& p) {
+    dgpe_status s;
+    if ((s = upload(p.tw[0], twiddles<T>(p.n[0], p.n[0]))) != DGPE_OK) return s;
+    if ((s = upload(p.tw[1], twiddles<T>(p.n[1], p.n[1]))) != DGPE_OK) return s;
+    if ((s = upload(p.tw[2], twiddles<T>(p.n[2] / 2, p.n[2] / 2))) != DGPE_OK) return s;
+    if ((s = upload(p.twr2c, twiddles<T>(p.n[2], p.n[2] / 2 + 1))) != DGPE_OK) return s;
+    if ((s = build_cn_tables<T>(p)) != DGPE_OK) return s;
+    DGPE_HIP(launch_ukern<T>(p));
+    DGPE_HIP(hipStreamSynchronize(p.stream));
+    return DGPE_OK;
+}
+
+bool finite3(const double* v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+dgpe_status check_ptr(const void* ptr, const char* what) {
+    if (!ptr) return fail(DGPE_EINVAL, std::string(what) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(ptr) % kAlign)
+        return fail(DGPE_EINVAL, std::string(what) + " is not 256-byte aligned");
+    return DGPE_OK;
+}
+
+// ---- the time loop ---------------------------------------------------------
+
+template <typename T>
+dgpe_status convolve_density(Plan& p, const void* psi, const double* sigma) {
+    DGPE_HIP(launch_r2c_density<T>(p, psi, sigma));
+    DGPE_HIP(launch_rows<T>(p, false));
+    DGPE_HIP(launch_xmul<T>(p));
+    DGPE_HIP(launch_rows<T>(p, true));
+    return DGPE_OK;
+}
+
+template <typename T>
+dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp) {
+    double* sigma = p.scal;
+    const int nb_x = cn_strided_blocks(p, 0);
+    for (int s = 0; s < nsteps; ++s) {
+        const double a = amp ? amp[s] : 1.0;
+        const double* sg = (p.imag && s > 0) ? sigma : nullptr;
+        dgpe_status st = convolve_density<T>(p, psi, sg);
+        if (st != DGPE_OK) return st;
+        DGPE_HIP(launch_c2r_step<T>(p, psi, sg, a));
+        DGPE_HIP(launch_cn_strided<T>(p, psi, 1, false, nullptr));
+        DGPE_HIP(launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr));
+        if (p.imag) DGPE_HIP(launch_norm_finalize(p, p.red, nb_x, sigma));
+    }
+    if (p.imag && nsteps > 0) DGPE_HIP(launch_scale<T>(p, psi, sigma));
+    return DGPE_OK;
+}
+
+template <typename T>
+dgpe_status observables_impl(Plan& p, const void* psi, double amp, dgpe_obs* out) {
+    dgpe_status st = convolve_density<T>(p, psi, nullptr);
+    if (st != DGPE_OK) return st;
+    DGPE_HIP(launch_c2r_phi<T>(p, p.phi));
+    int nb = 0;
+    DGPE_HIP(launch_observables<T>(p, psi, p.phi, amp, p.red, &nb));
+    DGPE_HIP(launch_reduce(p, p.red, nb, 10, p.scal + 2, nullptr));
+    double h[10];
+    DGPE_HIP(hipMemcpyAsync(h, p.scal + 2, sizeof(h), hipMemcpyDeviceToHost, p.stream));
+    DGPE_HIP(hipStreamSynchronize(p.stream));
+    const double dV = p.d[0] * p.d[1] * p.d[2];
+    const double nrm = h[0] * dV;
+    const double ekin =
+        0.5 * (h[1] / (p.d[0] * p.d[0]) + h[2] / (p.d[1] * p.d[1]) + h[3] / (p.d[2] * p.d[2])) * dV;
+    const double etrap = amp * h[4] * dV;
+    const double ec = 0.5 * p.g * h[5] * dV;
+    const double edd = 0.5 * p.gd * h[6] * dV;
+    out->norm = nrm;
+    out->e_kin = ekin;
+    out->e_trap = etrap;
+    out->e_contact = ec;
+    out->e_dd = edd;
+    out->energy = (ekin + etrap + ec + edd) / nrm;
+    out->mu = (ekin + etrap + 2.0 * ec + 2.0 * edd) / nrm;
+    const double mx = h[7] * dV / nrm, my = h[8] * dV / nrm, mz = h[9] * dV / nrm;
+    out->rms[0] = std::sqrt(mx);
+    out->rms[1] = std::sqrt(my);
+    out->rms[2] = std::sqrt(mz);
+    out->rms[3] = std::sqrt(mx + my + mz);
+    for (int i = 0; i < 10; ++i)
+        if (!std::isfinite(h[i])) return fail(DGPE_ENONFINITE, "observables: non-finite sum");
+    return DGPE_OK;
+}
+
+// ---- adjoint ---------------------------------------------------------------
+
+struct AdjLayout {
+    size_t ckpt, seg, lam, phin, phis, sums, part, scratch, end;
+    int nckpt;
+};
+
+AdjLayout adj_layout(const Plan& p, int nsteps, int K) {
+    AdjLayout L{};
+    const size_t nt = (size_t)p.n[0] * p.n[1] * p.n[2];
+    const size_t csz = p.f32 ? 8 : 16, rsz = p.f32 ? 4 : 8;
+    const size_t st = align_up(nt * csz);
+    L.nckpt = (nsteps + K - 1) / K;
+    size_t o = 0;
+    L.ckpt = o;
+    o += st * (size_t)std::max(L.nckpt, 1);
+    L.seg = o;
+    o += st * (size_t)K;
+    L.lam = o;
+    o += st;
+    L.phin = o;
+    o += align_up(nt * rsz);
+    L.phis = o;
+    o += align_up(nt * rsz);
+    L.sums = o;
+    o += align_up((size_t)(nsteps + 1) * 4 * sizeof(double));
+    L.part = o;
+    o += align_up(red_count_for(p.n, p.lc) * sizeof(double));
+    L.scratch = o;
+    o += align_up(16 * sizeof(double));
+    L.end = o;
+    return L;
+}
+
+template <typename T>
+dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* amp, int K,
+                         int objective, const void* target, char* ws, void* psi_final, double* J,
+                         double* dJ_damp, double* dJ_dtrap, void* dJ_dpsi0) {
+    const AdjLayout L = adj_layout(p, nsteps, K);
+    const size_t nt = (size_t)p.n[0] * p.n[1] * p.n[2];
+    const size_t st = align_up(nt * sizeof(T) * 2);
+    auto state = [&](size_t base, int i) { return (void*)(ws + base + st * (size_t)i); };
+    void* lam = ws + L.lam;
+    void* phin = ws + L.phin;
+    void* phis = ws + L.phis;
+    double* sums = (double*)(ws + L.sums);
+    double* part = (double*)(ws + L.part);
+    double* scratch = (double*)(ws + L.scratch);
+    // forward sweep, storing the state at the start of every segment
+    void* cur = state(L.seg, 0);
+    DGPE_HIP(launch_copy<T>(p, cur, psi0));
+    for (int s = 0; s < L.nckpt; ++s) {
+        const int n0 = s * K, len = std::min(K, nsteps - n0);
+        DGPE_HIP(launch_copy<T>(p, state(L.ckpt, s), cur));
+        dgpe_status stt = run_steps<T>(p, cur, len, amp + n0);
+        if (stt != DGPE_OK) return stt;
+    }
+    if (psi_final) DGPE_HIP(launch_copy<T>(p, psi_final, cur));
+    const double dV = p.d[0] * p.d[1] * p.d[2];
+    const double aN = amp[nsteps];
+    std::vector<double> hs((size_t)(nsteps + 1) * 4, 0.0);
+    double seed4[4] = {0, 0, 0, 0};
+    // seed
+    if (objective == DGPE_OBJ_ENERGY) {
+        dgpe_obs o;
+        dgpe_status stt = observables_impl<T>(p, cur, aN, &o);
+        if (stt != DGPE_OK) return stt;
+        *J = o.e_kin + o.e_trap + o.e_contact + o.e_dd;
+        // p.phi holds Phi[|psi_N|^2] from the observables
+        int nb = 0;
+        DGPE_HIP(launch_adj_seed<T>(p, lam, cur, p.phi, aN, part, &nb));
+        DGPE_HIP(launch_reduce(p, part, nb, 4, scratch, nullptr));
+        DGPE_HIP(hipMemcpyAsync(seed4, scratch, sizeof(seed4), hipMemcpyDeviceToHost, p.stream));
+    } else {
+        int nb = 0;
+        DGPE_HIP(launch_overlap<T>(p, target, cur, part, &nb));
+        DGPE_HIP(launch_reduce(p, part, nb, 2, scratch, nullptr));
+        double c2[2];
+        DGPE_HIP(hipMemcpyAsync(c2, scratch, sizeof(c2), hipMemcpyDeviceToHost, p.stream));
+        DGPE_HIP(hipStreamSynchronize(p.stream));
+        const double cr = c2[0] * dV, ci = c2[1] * dV;
+        *J = cr * cr + ci * ci;
+        const double coef[2] = {2.0 * dV * cr, 2.0 * dV * ci};
+        DGPE_HIP(launch_overlap_seed<T>(p, lam, target, coef));
+    }
+    // reverse sweep over segments
+    for (int s = L.nckpt - 1; s >= 0; --s) {
+        const int n0 = s * K, len = std::min(K, nsteps - n0);
+        DGPE_HIP(launch_copy<T>(p, state(L.seg, 0), state(L.ckpt, s)));
+        for (int i = 1; i < len; ++i) {
+            DGPE_HIP(launch_copy<T>(p, state(L.seg, i), state(L.seg, i - 1)));
+            dgpe_status stt = run_steps<T>(p, state(L.seg, i), 1, amp + n0 + i - 1);
+            if (stt != DGPE_OK) return stt;
+        }
+        for (int i = len - 1; i >= 0; --i) {
+            const int n = n0 + i;
+            void* psin = state(L.seg, i);
+            dgpe_status stt = convolve_density<T>(p, psin, nullptr);
+            if (stt != DGPE_OK) return stt;
+            DGPE_HIP(launch_c2r_phi<T>(p, phin));
+            DGPE_HIP(launch_cn_z<T>(p, lam, true));
+            DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
+            DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));
+            DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part));
+            DGPE_HIP(launch_reduce(p, part, r2c_blocks(p), 4, sums + (size_t)n * 4, nullptr));
+            DGPE_HIP(launch_rows<T>(p, false));
+            DGPE_HIP(launch_xmul<T>(p));
+            DGPE_HIP(launch_rows<T>(p, true));
+            DGPE_HIP(launch_c2r_phi<T>(p, phis));
+            DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
+        }
+    }
+    if (dJ_dpsi0) DGPE_HIP(launch_copy<T>(p, dJ_dpsi0, lam));
+    DGPE_HIP(hipMemcpyAsync(hs.data(), sums, (size_t)nsteps * 4 * sizeof(double),
+                            hipMemcpyDeviceToHost, p.stream));
+    DGPE_HIP(hipStreamSynchronize(p.stream));
+    for (int j = 0; j < 3; ++j) dJ_dtrap[j] = 0.0;
+    for (int n = 0; n < nsteps; ++n) {
+        dJ_damp[n] = p.dt * hs[(size_t)n * 4];
+        for (int j = 0; j < 3; ++j) dJ_dtrap[j] += p.dt * amp[n] * p.trap[j] * hs[(size_t)n * 4 + 1 + j];
+    }
+    dJ_damp[nsteps] = 0.0;
+    if (objective == DGPE_OBJ_ENERGY) {
+        dJ_damp[nsteps] = dV * seed4[0];
+        for (int j = 0; j < 3; ++j) dJ_dtrap[j] += dV * aN * p.trap[j] * seed4[1 + j];
+    }
+    for (int n = 0; n <= nsteps; ++n)
+        if (!std::isfinite(dJ_damp[n])) return fail(DGPE_ENONFINITE, "adjoint: non-finite gradient");
+    if (!std::isfinite(*J)) return fail(DGPE_ENONFINITE, "adjoint: non-finite objective");
+    return DGPE_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+const char* dgpe_status_string(dgpe_status s) {
+    switch (s) {
+        case DGPE_OK: return "DGPE_OK";
+        case DGPE_EINVAL: return "DGPE_EINVAL";
+        case DGPE_EUNSUPPORTED_SIZE: return "DGPE_EUNSUPPORTED_SIZE";
+        case DGPE_EWORKSPACE: return "DGPE_EWORKSPACE";
+        case DGPE_EHIP: return "DGPE_EHIP";
+        case DGPE_ENONFINITE: return "DGPE_ENONFINITE";
+        case DGPE_ESTATE: return "DGPE_ESTATE";
+    }
+    return "DGPE_UNKNOWN";
+}
+
+const char* dgpe_last_error(void) { return g_last_error.c_str(); }
+
+size_t dgpe_workspace_bytes(const int32_t n[3], uint32_t mode) {
+    if (!n) return 0;
+    int nn[3] = {n[0], n[1], n[2]};
+    for (int a = 0; a < 3; ++a)
+        if (!size_ok(nn[a])) return 0;
+    size_t offs[OFF_END + 1];
+    if (!layout(nn, (mode & DGPE_F32) != 0, offs, nullptr)) return 0;
+    return offs[OFF_END];
+}
+
+dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[3], double dt,
+                             const double trap[3], double g, double gd, double cutoff_R,
+                             uint32_t mode, void* workspace, size_t workspace_bytes,
+                             void* hip_stream) {
+    if (!out) return fail(DGPE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!n || !d || !trap) return fail(DGPE_EINVAL, "n, d and trap must be non-NULL");
+    if (mode & ~(DGPE_REAL | DGPE_F32)) return fail(DGPE_EINVAL, "unknown mode bits");
+    for (int a = 0; a < 3; ++a)
+        if (!size_ok(n[a]))
+            return fail(DGPE_EUNSUPPORTED_SIZE,
+                        "grid size " + std::to_string(n[a]) +
+                            " must be even, of the form 2^a 3^b, and in [4, 1024]");
+    for (int a = 0; a < 3; ++a)
+        if (!(d[a] > 0) || !std::isfinite(d[a])) return fail(DGPE_EINVAL, "spacings must be finite and > 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(DGPE_EINVAL, "dt must be finite and > 0");
+    if (!finite3(trap) || !std::isfinite(g) || !std::isfinite(gd) || !std::isfinite(cutoff_R))
+        return fail(DGPE_EINVAL, "trap, g, gd and cutoff must be finite");
+    const bool f32 = (mode & DGPE_F32) != 0;
+    int nn[3] = {n[0], n[1], n[2]};
+    size_t offs[OFF_END + 1];
+    Launch lc;
+    if (!layout(nn, f32, offs, &lc))
+        return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape fits this grid");
+    dgpe_status st = check_ptr(workspace, "workspace");
+    if (st != DGPE_OK) return fail(DGPE_EWORKSPACE, dgpe_last_error());
+    if (workspace_bytes < offs[OFF_END])
+        return fail(DGPE_EWORKSPACE, "workspace too small: need " + std::to_string(offs[OFF_END]) +
+                                         " bytes");
+    dgpe_plan_s* p = new (std::nothrow) dgpe_plan_s();
+    if (!p) return fail(DGPE_EINVAL, "out of host memory");
+    for (int a = 0; a < 3; ++a) {
+        p->n[a] = n[a];
+        p->d[a] = d[a];
+        p->trap[a] = trap[a];
+    }
+    p->dt = dt;
+    p->g = g;
+    p->gd = gd;
+    p->R = cutoff_R > 0 ? cutoff_R : 0.5 * std::min({n[0] * d[0], n[1] * d[1], n[2] * d[2]});
+    p->imag = (mode & DGPE_REAL) == 0;
+    p->f32 = f32;
+    p->stream = (hipStream_t)hip_stream;
+    p->lc = lc;
+    hipGetDevice(&p->device);
+    char* ws = (char*)workspace;
+    p->ws = ws;
+    p->ws_bytes = workspace_bytes;
+    p->spec = ws + offs[OFF_SPEC];
+    p->phi = ws + offs[OFF_PHI];
+    p->ukern = ws + offs[OFF_UK];
+    p->tw[0] = ws + offs[OFF_TWX];
+    p->tw[1] = ws + offs[OFF_TWY];
+    p->tw[2] = ws + offs[OFF_TWZ];
+    p->twr2c = ws + offs[OFF_TWR];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 2; ++c) p->cntab[a][c] = ws + offs[OFF_CN0 + 2 * a + c];
+    p->red = (double*)(ws + offs[OFF_RED]);
+    p->scal = (double*)(ws + offs[OFF_SCAL]);
+    p->red_count = red_count_for(nn, lc);
+    p->fx = factor(n[0]);
+    p->fy = factor(n[1]);
+    p->fz = factor(n[2] / 2);
+    st = f32 ? build_tables<float>(*p) : build_tables<double>(*p);
+    if (st != DGPE_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return DGPE_OK;
+}
+
+dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (!std::isfinite(value)) return fail(DGPE_EINVAL, "value must be finite");
+    Plan& p = *plan;
+    switch (param) {
+        case DGPE_PARAM_G: p.g = value; return DGPE_OK;
+        case DGPE_PARAM_GD: p.gd = value; return DGPE_OK;
+        case DGPE_PARAM_TRAP_NU: p.trap[0] = value; return DGPE_OK;
+        case DGPE_PARAM_TRAP_LAMBDA: p.trap[1] = value; return DGPE_OK;
+        case DGPE_PARAM_TRAP_GAMMA: p.trap[2] = value; return DGPE_OK;
+        case DGPE_PARAM_DT:
+            if (!(value > 0)) return fail(DGPE_EINVAL, "dt must be > 0");
+            p.dt = value;
+            break;
+        case DGPE_PARAM_REAL_TIME:
+            if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "REAL_TIME takes 0 or 1");
+            p.imag = value == 0.0;
+            break;
+        default: return fail(DGPE_EINVAL, "unknown parameter");
+    }
+    DGPE_HIP(hipStreamSynchronize(p.stream));
+    return p.f32 ? build_cn_tables<float>(p) : build_cn_tables<double>(p);
+}
+
+dgpe_status dgpe_plan_set_stream(dgpe_plan plan, void* hip_stream) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    plan->stream = (hipStream_t)hip_stream;
+    return DGPE_OK;
+}
+
+dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    if (nsteps < 0) return fail(DGPE_EINVAL, "nsteps must be >= 0");
+    if (amp)
+        for (int i = 0; i < nsteps; ++i)
+            if (!std::isfinite(amp[i])) return fail(DGPE_EINVAL, "amp must be finite");
+    return plan->f32 ? run_steps<float>(*plan, psi, nsteps, amp)
+                     : run_steps<double>(*plan, psi, nsteps, amp);
+}
+
+dgpe_status dgpe_potential(dgpe_plan plan, const void* psi, void* phi) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    if ((st = check_ptr(phi, "phi")) != DGPE_OK) return st;
+    Plan& p = *plan;
+    if (p.f32) {
+        if ((st = convolve_density<float>(p, psi, nullptr)) != DGPE_OK) return st;
+        DGPE_HIP(launch_c2r_phi<float>(p, phi));
+    } else {
+        if ((st = convolve_density<double>(p, psi, nullptr)) != DGPE_OK) return st;
+        DGPE_HIP(launch_c2r_phi<double>(p, phi));
+    }
+    return DGPE_OK;
+}
+
+dgpe_status dgpe_energy_mu_rms(dgpe_plan plan, const void* psi, double amp, dgpe_obs* out) {
+    if (!plan || !out) return fail(DGPE_EINVAL, "plan and out must be non-NULL");
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    if (!std::isfinite(amp)) return fail(DGPE_EINVAL, "amp must be finite");
+    return plan->f32 ? observables_impl<float>(*plan, psi, amp, out)
+                     : observables_impl<double>(*plan, psi, amp, out);
+}
+
+size_t dgpe_adjoint_workspace_bytes(dgpe_plan plan, int32_t nsteps, int32_t ckpt_every) {
+    if (!plan || nsteps < 1 || ckpt_every < 1) return 0;
+    return adj_layout(*plan, nsteps, std::min(ckpt_every, nsteps)).end;
+}
+
+dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, const double* amp,
+                              int32_t ckpt_every, int32_t objective, const void* target,
+                              void* adj_ws, size_t adj_ws_bytes, void* psi_final, double* J,
+                              double* dJ_damp, double dJ_dtrap[3], void* dJ_dpsi0) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    Plan& p = *plan;
+    if (p.imag) return fail(DGPE_ESTATE, "the adjoint needs a real-time plan");
+    if (nsteps < 1 || ckpt_every < 1) return fail(DGPE_EINVAL, "nsteps and ckpt_every must be >= 1");
+    if (!amp || !J || !dJ_damp || !dJ_dtrap) return fail(DGPE_EINVAL, "amp, J, dJ_damp, dJ_dtrap required");
+    for (int i = 0; i <= nsteps; ++i)
+        if (!std::isfinite(amp[i])) return fail(DGPE_EINVAL, "amp must be finite");
+    if (objective != DGPE_OBJ_ENERGY && objective != DGPE_OBJ_OVERLAP)
+        return fail(DGPE_EINVAL, "unknown objective");
+    dgpe_status st = check_ptr(psi0, "psi0");
+    if (st != DGPE_OK) return st;
+    if (objective == DGPE_OBJ_OVERLAP && (st = check_ptr(target, "target")) != DGPE_OK) return st;
+    if (psi_final && (st = check_ptr(psi_final, "psi_final")) != DGPE_OK) return st;
+    if (dJ_dpsi0 && (st = check_ptr(dJ_dpsi0, "dJ_dpsi0")) != DGPE_OK) return st;
+    const int K = std::min(ckpt_every, nsteps);
+    if ((st = check_ptr(adj_ws, "adj_ws")) != DGPE_OK) return fail(DGPE_EWORKSPACE, dgpe_last_error());
+    if (adj_ws_bytes < adj_layout(p, nsteps, K).end)
+        return fail(DGPE_EWORKSPACE, "adjoint workspace too small");
+    return p.f32 ? adjoint_impl<float>(p, psi0, nsteps, amp, K, objective, target, (char*)adj_ws,
+                                       psi_final, J, dJ_damp, dJ_dtrap, dJ_dpsi0)
+                 : adjoint_impl<double>(p, psi0, nsteps, amp, K, objective, target, (char*)adj_ws,
+                                        psi_final, J, dJ_damp, dJ_dtrap, dJ_dpsi0);
+}
+
+void dgpe_plan_destroy(dgpe_plan plan) { delete plan; }
+
+}  // extern "C"

@@ -1,0 +1,298 @@
+// Device building blocks of libdgpe for gfx950 (CDNA4, wave64):
+// complex arithmetic, radix-2/3/4/8 DFT butterflies, one Stockham stage on a
+// batch of sequences resident in LDS, and cheap division by plan constants.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dgpe_internal.h"
+
+namespace dgpe {
+
+// ---------------------------------------------------------------------------
+// complex numbers: interleaved (re, im), 8 B (float) or 16 B (double)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { return cx<T>{a, b}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator*(T s, cx<T> a) { return {s * a.x, s * a.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ T abs2(cx<T> a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+__device__ __forceinline__ float exp_of(float x) { return expf(x); }
+__device__ __forceinline__ double exp_of(double x) { return exp(x); }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot90(cx<T> a) {
+    return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// quotient by a plan constant d (2 <= d, n * d < 2^32): q = umulhi(n, ceil(2^32/d))
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return __umulhi(n, f.m); }
+
+// ---------------------------------------------------------------------------
+// small DFTs, forward sign exp(-2 pi i jk/R); INV gives the conjugate kernel
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__device__ __forceinline__ void dft2(cx<T>& a0, cx<T>& a1) {
+    cx<T> t = a0 - a1;
+    a0 = a0 + a1;
+    a1 = t;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3(cx<T>* v) {
+    const T h = T(0.5);
+    const T s = T(0.86602540378443864676372317075293618);
+    cx<T> t1 = v[1] + v[2];
+    cx<T> t2 = v[0] - h * t1;
+    cx<T> d = s * (v[1] - v[2]);
+    cx<T> t3 = rot90<T, INV>(d);
+    v[0] = v[0] + t1;
+    v[1] = t2 + t3;
+    v[2] = t2 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+    cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = rot90<T, INV>(a1 - a3);
+    a0 = t0 + t2;
+    a2 = t0 - t2;
+    a1 = t1 + t3;
+    a3 = t1 - t3;
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+    const T c = T(0.70710678118654752440084436210484904);
+    cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<T, INV>(e0, e1, e2, e3);
+    dft4<T, INV>(o0, o1, o2, o3);
+    // o_k *= W8^k, W8 = exp(-i pi/4) (conjugated for INV)
+    cx<T> w1 = INV ? cx<T>{c, c} : cx<T>{c, -c};
+    cx<T> w3 = INV ? cx<T>{-c, c} : cx<T>{-c, -c};
+    o1 = cmul(o1, w1);
+    o2 = rot90<T, INV>(o2);
+    o3 = cmul(o3, w3);
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + o1;
+    v[5] = e1 - o1;
+    v[2] = e2 + o2;
+    v[6] = e2 - o2;
+    v[3] = e3 + o3;
+    v[7] = e3 - o3;
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+    if constexpr (R == 2) dft2<T, INV>(v[0], v[1]);
+    else if constexpr (R == 3) dft3<T, INV>(v);
+    else if constexpr (R == 4) dft4<T, INV>(v[0], v[1], v[2], v[3]);
+    else dft8<T, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One self-sorting (Stockham) radix-R stage over B = 2^logB sequences of
+// length L held in LDS; element e of sequence b lives at buf[e * ES + b].
+// Butterfly j (0 <= j < L/R) with k = j mod Ns reads elements j + r L/R,
+// multiplies element r by W_L^{r k L/(Ns R)}, applies the R-point DFT and
+// writes to ((j - k) R + k + r Ns).  All reads of a stage complete (barrier)
+// before its writes, so the stage runs in place with registers as staging.
+// Each thread owns at most MAXB butterflies (the launch guarantees it).
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool INV, int MAXB>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, int ES, int L, int logB, int Ns,
+                                          const cx<T>* tw, int tid, int nthr) {
+    const int LR = L / R;
+    const int nb = LR << logB;
+    const int tws = L / (Ns * R);
+    const int bmask = (1 << logB) - 1;
+    cx<T> v[MAXB][R];
+    int obase[MAXB];
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int t = tid + q * nthr;
+        if (t < nb) {
+            const int b = t & bmask;
+            const int j = t >> logB;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * LR) * ES + b];
+            if (k != 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> w = tw[r * k * tws];
+                    v[q][r] = INV ? cmulc(v[q][r], w) : cmul(v[q][r], w);
+                }
+            }
+            obase[q] = ((j - k) * R + k) * ES + b;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        const int t = tid + q * nthr;
+        if (t < nb) {
+            dftR<T, R, INV>(v[q]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[obase[q] + r * Ns * ES] = v[q][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Whole FFT of length f.L on the LDS batch (forward: exp(-2 pi i ...), INV:
+// exp(+2 pi i ...), both unnormalised).  The caller synchronises before the
+// first stage; the last stage ends with a barrier.  EMAX bounds the elements
+// per thread: (L << logB) <= EMAX * nthr.
+template <typename T, bool INV, int EMAX>
+__device__ __forceinline__ void lds_fft(cx<T>* buf, int ES, const FftDesc& f, int logB,
+                                        const cx<T>* tw, int tid, int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < f.nstages; ++s) {
+        const int R = f.radix[s];
+        if (R == 8) fft_stage<T, 8, INV, (EMAX + 7) / 8>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
+        else if (R == 4) fft_stage<T, 4, INV, (EMAX + 3) / 4>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
+        else if (R == 3) fft_stage<T, 3, INV, (EMAX + 2) / 3>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
+        else fft_stage<T, 2, INV, (EMAX + 1) / 2>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
+        Ns *= R;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// block-wide FP64 sum (deterministic fixed tree: wave shuffles, then LDS)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sums v over the block; the result is valid in thread 0.  `scratch` holds
+// one double per wave.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) r += scratch[w];
+    return r;
+}
+
+}  // namespace dgpe
+
+namespace dgpe {
+
+// ---------------------------------------------------------------------------
+// Crank-Nicolson solve of one line split into segments of S points.
+//
+// (1 - A D) x = (1 + A D) u on a line of N points with zero ghosts is a
+// constant tridiagonal system; its Thomas factors (m, alpha, gamma) depend
+// only on the position, so they are plan tables.  Each thread owns the
+// segment [e0, e0 + cnt) of one line in registers (v, holding u on entry) and
+//   1. forms the right-hand side from its points and the neighbours `left`
+//      (u_{e0-1}) and `right` (u_{e0+cnt}), zero beyond the line;
+//   2. runs forward elimination from a zero carry, publishes its last value;
+//   3. adds P_i * (true d_{e0-1}), where the true value follows from the
+//      published values of the segments to its left (linear recurrence);
+//   4. runs back substitution from a zero carry, publishes its first value,
+//      and adds Q_i * (true x_{e0+cnt}) from the segments to its right.
+// The result equals plain Thomas elimination up to rounding (no truncation).
+// All threads of the block must call this (it contains two barriers);
+// threads without a segment pass cnt = 0.  dl and xf are LDS arrays of
+// nseg * nlines entries, indexed [seg * nlines + line].
+// ---------------------------------------------------------------------------
+template <typename T, int S>
+__device__ __forceinline__ void cn_segment_solve(cx<T> (&v)[S], int cnt, cx<T> left, cx<T> right,
+                                                 cx<T> A, const cx<T>* __restrict__ tab, int N,
+                                                 int e0, int seg, int nseg, cx<T>* dl, cx<T>* xf,
+                                                 int line, int nlines) {
+    const cx<T>* tm = tab + TAB_M * N;
+    const cx<T>* ta = tab + TAB_ALPHA * N;
+    const cx<T>* tg = tab + TAB_GAMMA * N;
+    const cx<T>* tp = tab + TAB_P * N;
+    const cx<T>* tq = tab + TAB_Q * N;
+    const cx<T> diag = {T(1) - T(2) * A.x, -T(2) * A.y};
+    // 1. right-hand side (1 + A D) u
+    cx<T> prev = left;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i < cnt) {
+            const cx<T> cur = v[i];
+            cx<T> nxt = right;
+            if (i + 1 < S && i + 1 < cnt) nxt = v[(i + 1 < S) ? i + 1 : i];
+            v[i] = cmul(A, prev + nxt) + cmul(diag, cur);
+            prev = cur;
+        }
+    }
+    // 2. forward elimination with a zero carry
+    cx<T> dcur = {T(0), T(0)};
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i < cnt) {
+            const int e = e0 + i;
+            dcur = cmul(ta[e], dcur) + cmul(tm[e], v[i]);
+            v[i] = dcur;
+        }
+    }
+    if (cnt > 0) dl[seg * nlines + line] = dcur;
+    __syncthreads();
+    if (cnt > 0) {
+        // 3. true d_{e0-1} from the segments on the left
+        cx<T> c = {T(0), T(0)};
+        for (int k = 0; k < seg; ++k) c = dl[k * nlines + line] + cmul(tp[k * S + S - 1], c);
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (i < cnt) v[i] = v[i] + cmul(tp[e0 + i], c);
+        // 4. back substitution with a zero carry
+        cx<T> xcur = {T(0), T(0)};
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
+            if (i < cnt) {
+                xcur = v[i] + cmul(tg[e0 + i], xcur);
+                v[i] = xcur;
+            }
+        }
+        xf[seg * nlines + line] = xcur;
+    }
+    __syncthreads();
+    if (cnt > 0) {
+        cx<T> c = {T(0), T(0)};
+        for (int k = nseg - 1; k > seg; --k) c = xf[k * nlines + line] + cmul(tq[k * S], c);
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (i < cnt) v[i] = v[i] + cmul(tq[e0 + i], c);
+    }
+}
+
+}  // namespace dgpe

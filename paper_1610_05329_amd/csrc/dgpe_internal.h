@@ -1,0 +1,121 @@
+// Internal declarations shared by the libdgpe host code and kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dgpe {
+
+constexpr int kMaxStages = 12;
+
+// Factorisation of one FFT length into radices 8/4/2 (first) and 3 (last).
+struct FftDesc {
+    int L;
+    int nstages;
+    int radix[kMaxStages];
+};
+
+// n / d as umulhi(n, m) with m = ceil(2^32 / d); exact for n * d < 2^32.
+struct FastDiv {
+    uint32_t d;
+    uint32_t m;
+};
+
+// Per-axis Crank-Nicolson tables (complex, plan precision), each of length N,
+// stored back to back: for (1 - A D) x = (1 + A D) u with zero ghosts,
+//   d_i = alpha_i d_{i-1} + m_i r_i            (forward elimination)
+//   x_i = d_i + gamma_i x_{i+1}                (back substitution)
+// and, for segments of S points, the carry products
+//   P_i = prod_{j = seg start}^{i} alpha_j,  Q_i = prod_{j = i}^{seg end - 1} gamma_j.
+enum { TAB_M = 0, TAB_ALPHA = 1, TAB_GAMMA = 2, TAB_P = 3, TAB_Q = 4, TAB_COUNT = 5 };
+
+// Launch parameters of the seven passes for one plan (host side).
+struct Launch {
+    int threads;  // block size of FFT passes
+    int logB_z;   // lines per block in the z passes (r2c / c2r)
+    int logB_y;   // rows per block in the y pass
+    int logB_x;   // columns per block in the x pass
+    int seg[3];   // Thomas segment length per axis
+    int logZB[3]; // columns per block of the strided sweeps (x, y)
+};
+
+struct Plan {
+    int n[3];
+    double d[3];
+    double dt;
+    double trap[3];
+    double g, gd, R;
+    bool imag, f32;
+    hipStream_t stream;
+    int device;
+    // workspace carve-up (device pointers)
+    char* ws;
+    size_t ws_bytes;
+    void* spec;         // [Nz/2+1][Nx][Ny] complex
+    void* phi;          // [Nx][Ny][Nz] real (observables / adjoint scratch)
+    void* ukern;        // [Nz/2+1][Nx/2+1][Ny/2+1] real, U_R / Nt
+    void* tw[3];        // twiddles W_L^m for the x, y FFTs (L = Nx, Ny) and the z FFT (L = Nz/2)
+    void* twr2c;        // W_Nz^k, k = 0..Nz/2
+    void* cntab[3][2];  // per axis: [0] forward A, [1] conj(A) (adjoint)
+    double* red;        // reduction partials
+    double* scal;       // device scalars: [0] sigma (pending 1/norm), [1..] spare
+    size_t red_count;
+    FftDesc fx, fy, fz;
+    Launch lc;
+};
+
+size_t workspace_layout(const int n[3], bool f32, size_t* offs /* [16] or null */);
+
+// ---- kernel launchers (templated on precision in the .hip files) ----------
+// Each returns hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_r2c_density(const Plan& p, const void* psi, const double* sigma);
+template <typename T>
+hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin, const void* phin,
+                                double amp, double* partials);
+template <typename T>
+hipError_t launch_rows(const Plan& p, bool inverse);
+template <typename T>
+hipError_t launch_xmul(const Plan& p);
+template <typename T>
+hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double amp);
+template <typename T>
+hipError_t launch_c2r_phi(const Plan& p, void* phi_out);
+template <typename T>
+hipError_t launch_cn_z(const Plan& p, void* f, bool conjugate);
+template <typename T>
+hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate, double* norm_partials);
+template <typename T>
+hipError_t launch_scale(const Plan& p, void* psi, const double* sigma);
+template <typename T>
+hipError_t launch_ukern(const Plan& p);
+template <typename T>
+hipError_t launch_observables(const Plan& p, const void* psi, const void* phi, double amp,
+                              double* partials, int* nblocks);
+template <typename T>
+hipError_t launch_adj_update(const Plan& p, void* lam, const void* psin, const void* phin,
+                             const void* phis, double amp);
+template <typename T>
+hipError_t launch_adj_seed(const Plan& p, void* lam, const void* psi, const void* phi, double amp,
+                           double* partials, int* nblocks);
+template <typename T>
+hipError_t launch_overlap(const Plan& p, const void* target, const void* psi, double* partials,
+                          int* nblocks);
+template <typename T>
+hipError_t launch_overlap_seed(const Plan& p, void* lam, const void* target, const double* coef);
+template <typename T>
+hipError_t launch_copy(const Plan& p, void* dst, const void* src);
+
+// Deterministic fixed-order reduction of partials[nblocks][width] into
+// out[width] (FP64, Neumaier-compensated); optional 1/(sum[0] dV) into sigma.
+hipError_t launch_reduce(const Plan& p, const double* partials, int nblocks, int width, double* out,
+                         double* sigma_out);
+// sigma = 1 / (sum of norm partials * dV)
+hipError_t launch_norm_finalize(const Plan& p, const double* partials, int nblocks, double* sigma);
+
+int cn_strided_blocks(const Plan& p, int axis);
+int observables_blocks(const Plan& p);
+int r2c_blocks(const Plan& p);
+
+}  // namespace dgpe
