@@ -1,0 +1,294 @@
+#!/usr/bin/env python3
+"""Throughput of the split-step Crank-Nicolson time step of the 3D dipolar GPE
+on one MI355X: grid-point-steps per second at 256^3.
+
+Default run (one JSON line on stdout):
+  headline  FP32 (complex64 passes, FP64 reductions) imaginary-time steps of the
+            256^3 workload (dx = 0.1, dt = 0.001, trap (1, 1, 0.5), g = 100,
+            gd = 60), input resident in HBM, K timed steps after W warm-up
+            steps, bracketed by device synchronisation (the paper's timing
+            rule: only the iteration loop is timed, program summary, Testing
+            results).
+  variants  the same workload in FP64, and the FP32 real-time adjoint
+            (forward, recompute and reverse sweeps, per forward step).
+  roofline  per-pass HIP event timing of the dominant pass on the plan's
+            stream against its algorithmic HBM bytes; HBM traffic from the
+            committed rocprofv3 counter summary when it matches the sources.
+  cpu_baseline  the FP64 oracle on the host on a bounded sample (a few steps
+            of the same workload).
+
+Other modes:
+  --profile-run        headline steps only (for rocprofv3 runs)
+  --copy-calibration   a plain device copy of known size (counter calibration)
+  --summarize DIR      turn rocprofv3 CSV output under DIR into profiles/ text
+"""
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cubed.json")
+KERNEL_OF_PASS = {
+    "r2c_z": "k_r2c_z", "fft_y": "k_rows", "fft_x_mul": "k_xmul", "ifft_y": "k_rows",
+    "c2r_z_nonlinear_cn_z": "k_c2r_step", "cn_y": "k_cn_strided", "cn_x": "k_cn_strided",
+    "norm_reduce": "k_reduce",
+}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1610_05329_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(cfg):
+    return {
+        "workload": f"{cfg.n[0]}x{cfg.n[1]}x{cfg.n[2]} imaginary-time split step, dx={cfg.d[0]}, "
+                    f"dt={cfg.dt}, trap=({cfg.trap[0]},{cfg.trap[1]},{cfg.trap[2]}), g={cfg.g}, gd={cfg.gd}, "
+                    f"cutoff R=L/2, seeded Gaussian + 1e-3 noise",
+        "grid": list(cfg.n), "points": cfg.npoints,
+    }
+
+
+CHUNK = 50  # the 256^3 imaginary-time parameters collapse after ~90 steps
+
+
+def timed_steps(torch, plan, psi, psi_init, steps, warmup):
+    """Time `steps` steps in chunks of at most CHUNK, each chunk restarting from
+    psi_init (device copy, inside the timed region) so that every timed step
+    works on a regular state."""
+    psi.copy_(psi_init)
+    plan.step(psi, min(warmup, CHUNK))
+    torch.cuda.synchronize()
+    stream = plan.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done = 0
+    while done < steps:
+        k = min(CHUNK, steps - done)
+        psi.copy_(psi_init)
+        plan.step(psi, k)
+        done += k
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / 1000.0
+
+
+def traffic_for(kernel, launches_per_step_of_kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when absent or taken from other sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE))
+    if t.get("source_hash") != source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k["hbm_bytes_per_dispatch"]
+
+
+def cpu_baseline(cfg, psi0, steps):
+    from oracle import dgpe_oracle as O
+    p = O.Params.from_config(cfg)
+    V0 = O.trap_base(p)
+    psi = psi0.copy()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        psi = O.step(p, psi, 1.0, V0)
+    dt = time.perf_counter() - t0
+    return {"value": cfg.npoints * steps / dt, "unit": "grid-point-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} FP64 oracle steps of the same {cfg.n[0]}^3 imaginary-time workload "
+                      f"({dt:.1f} s; numpy, single-threaded FFT and elementwise work)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--summarize", metavar="DIR")
+    ap.add_argument("--summary-name", default="")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--adjoint-steps", type=int, default=40)
+    args = ap.parse_args()
+
+    if args.summarize:
+        summarize(args.summarize, args.summary_name)
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU slab decomposition "
+              "is a design, not an implementation (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1610_05329_amd as dg
+    import workloads as W
+
+    if args.copy_calibration:
+        n = 64 << 20  # 64 Mi floats = 256 MiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 5 copies of {n * 4} bytes")
+        return
+
+    cfg = W.CONFIGS["C3"]
+    log(f"[bench] workload {cfg.n} imaginary time; preparing seeded state")
+    psi0 = W.noisy_gaussian(cfg)
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=torch.complex64)
+    psi_init = plan.new_state(psi0)
+    psi = psi_init.clone()
+    if args.profile_run:
+        for k in (args.warmup, args.steps):
+            psi.copy_(psi_init)
+            plan.step(psi, min(k, CHUNK))
+        torch.cuda.synchronize()
+        log("[bench] profile run done")
+        return
+
+    wall, ev = timed_steps(torch, plan, psi, psi_init, args.steps, args.warmup)
+    value = cfg.npoints * args.steps / wall
+    log(f"[bench] FP32: {args.steps} steps in {wall * 1e3:.2f} ms wall ({ev * 1e3:.2f} ms events)")
+    assert torch.isfinite(torch.view_as_real(psi)).all().item(), "non-finite state"
+
+    # roofline: per-pass events over a second timed region
+    psi.copy_(psi_init)
+    ms, tot = plan.step_profiled(psi, min(args.steps, CHUNK))
+    pbytes = plan.pass_bytes()
+    per_step_bytes = sum(pbytes.values())
+    share = {k: v for k, v in ms.items() if v > 0}
+    dom = max(share, key=share.get)  # longest average launch
+    ach = pbytes[dom] / (ms[dom] * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm", "kernel": KERNEL_OF_PASS[dom], "pass": dom, "achieved": round(ach, 1),
+        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+        "traffic": traffic_for(KERNEL_OF_PASS[dom], 1),
+        "avg_launch_ms": round(ms[dom], 5), "algorithmic_bytes_per_launch": pbytes[dom],
+        "per_pass_ms": {k: round(v, 5) for k, v in ms.items()},
+        "per_pass_GBs": {k: round(pbytes[k] / (ms[k] * 1e-3) / 1e9, 1) for k in share},
+        "step_algorithmic_bytes": per_step_bytes,
+        "step_effective_GBs": round(per_step_bytes * args.steps / wall / 1e9, 1),
+        "step_frac_of_peak": round(per_step_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    log(f"[bench] dominant pass {dom}: {ach:.0f} GB/s; step effective "
+        f"{roofline['step_effective_GBs']} GB/s")
+
+    variants = {}
+    if not args.no_variants:
+        plan64 = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=torch.complex128)
+        init64 = plan64.new_state(psi0)
+        psi64 = init64.clone()
+        w64, _ = timed_steps(torch, plan64, psi64, init64, args.steps, args.warmup)
+        b64 = sum(plan64.pass_bytes().values())
+        variants["f64"] = {"value": cfg.npoints * args.steps / w64, "ms_per_step": w64 * 1e3 / args.steps,
+                           "step_effective_GBs": round(b64 * args.steps / w64 / 1e9, 1)}
+        log(f"[bench] FP64: {w64 * 1e3 / args.steps:.3f} ms/step")
+        del plan64, psi64, init64
+        torch.cuda.empty_cache()
+        # adjoint: real time, FP32, energy objective, checkpoints every 10 steps
+        na = args.adjoint_steps
+        plan_a = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=torch.complex64)
+        psia = plan_a.new_state(psi0)
+        amp = np.ones(na + 1)
+        plan_a.adjoint(psia, amp[:3], ckpt_every=2)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = plan_a.adjoint(psia, amp, ckpt_every=10)
+        torch.cuda.synchronize()
+        wa = time.perf_counter() - t0
+        variants["adjoint_f32"] = {"value": cfg.npoints * na / wa, "ms_per_step": wa * 1e3 / na,
+                                   "steps": na, "ckpt_every": 10, "objective": "energy",
+                                   "J": out["J"]}
+        log(f"[bench] adjoint FP32: {wa * 1e3 / na:.3f} ms per forward step")
+        del plan_a, psia, out
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline: {args.cpu_steps} steps")
+        cpu = cpu_baseline(cfg, psi0, args.cpu_steps)
+
+    line = {
+        "metric": "grid-point-steps/sec at 256^3 (FP32 plain imaginary-time step)",
+        "value": value, "unit": "grid-point-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded Gaussian + uniform noise, generated on the host)",
+        "config": workload(cfg), "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 summaries
+# ---------------------------------------------------------------------------
+
+def _short(name):
+    for k in ("k_r2c_z", "k_rows", "k_xmul", "k_c2r_step", "k_c2r_phi", "k_cn_strided", "k_cn_z",
+              "k_reduce", "k_scale", "k_observables", "k_ukern"):
+        if k in name:
+            tmpl = name[name.find(k):]
+            return tmpl.split("(")[0]
+    return name.split("(")[0][:60]
+
+
+def summarize(d, name):
+    """Write profiles/<name>.txt (kernel stats) or the traffic JSON from rocprofv3
+    CSV output found under d."""
+    import csv
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    ctr = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if stats:
+        rows = list(csv.DictReader(open(stats[0])))
+        out = [f"# rocprofv3 kernel statistics ({name})", f"# source: {os.path.relpath(stats[0], ROOT)}",
+               f"{'kernel':<48} {'calls':>6} {'avg_us':>10} {'total_ms':>10} {'pct':>6}"]
+        for r in rows:
+            out.append(f"{_short(r['Name']):<48} {int(r['Calls']):>6} "
+                       f"{float(r['AverageNs']) / 1e3:>10.2f} {float(r['TotalDurationNs']) / 1e6:>10.3f} "
+                       f"{float(r['Percentage']):>6.2f}")
+        open(os.path.join(ROOT, "profiles", f"{name}.txt"), "w").write("\n".join(out) + "\n")
+        print("\n".join(out))
+    for c in ctr:
+        rows = list(csv.DictReader(open(c)))
+        agg = {}
+        for r in rows:
+            k = _short(r.get("Kernel_Name", r.get("Kernel-Name", "")))
+            cn = r.get("Counter_Name", "")
+            v = float(r.get("Counter_Value", 0))
+            a = agg.setdefault((k, cn), [0.0, 0])
+            a[0] += v
+            a[1] += 1
+        out = {f"{k}|{cn}": {"mean_per_dispatch": s / max(n, 1), "dispatch_rows": n}
+               for (k, cn), (s, n) in agg.items()}
+        path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
+        json.dump({"source": os.path.relpath(c, ROOT), "counters": out}, open(path, "w"), indent=1)
+        print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()

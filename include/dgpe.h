@@ -164,6 +164,27 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
                               void* adj_ws, size_t adj_ws_bytes, void* psi_final, double* J,
                               double* dJ_damp, double dJ_dtrap[3], void* dJ_dpsi0);
 
+/* Pass kinds of one step, in launch order (indices of the arrays below):
+ *   0 density + R2C along z      1 FFT along y
+ *   2 FFT along x, U_R multiply, inverse FFT along x
+ *   3 inverse FFT along y        4 C2R along z + nonlinear phase + CN along z
+ *   5 CN along y                 6 CN along x (+ norm partials, imaginary time)
+ *   7 norm reduction (imaginary time) */
+#define DGPE_NPASS 8
+
+/* Algorithmic HBM bytes of one launch of each pass for this plan: every array
+ * a pass must read or write, counted once (state 2s bytes per point, half
+ * spectrum 2s per complex value, kernel table s per entry, s = real size).
+ * Host only; no device work. */
+dgpe_status dgpe_pass_bytes(dgpe_plan plan, double bytes[DGPE_NPASS]);
+
+/* Same work as dgpe_step, with a HIP event pair around every pass on the
+ * plan's stream; synchronises and writes the mean milliseconds per launch of
+ * each pass kind into ms[DGPE_NPASS] (0 for passes that did not run) and the
+ * wall time of the whole call into *total_ms (nullable).  For measurement. */
+dgpe_status dgpe_step_profiled(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp,
+                               double ms[DGPE_NPASS], double* total_ms);
+
 /* Release the plan's host metadata (the workspace stays with the caller). */
 void dgpe_plan_destroy(dgpe_plan plan);
 

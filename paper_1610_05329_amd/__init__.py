@@ -172,6 +172,26 @@ class Plan:
         return {"J": J.value, "dJ_damp": dJ_da, "dJ_dtrap": dJ_dt, "psi_final": psi_f,
                 "dJ_dpsi0": lam0}
 
+    def pass_bytes(self):
+        """Algorithmic HBM bytes per launch of each pass (dict by pass name)."""
+        b = np.zeros(_lib.NPASS)
+        check(self.lib.dgpe_pass_bytes(self.handle, b.ctypes.data_as(_lib.P_double)))
+        return dict(zip(_lib.PASS_NAMES, b.tolist()))
+
+    def step_profiled(self, psi, nsteps=1, amp=None):
+        """dgpe_step with HIP events around every pass; returns (mean ms per launch
+        by pass name, total ms).  Synchronises."""
+        self._check_state(psi)
+        amp_p = None
+        if amp is not None:
+            a = np.ascontiguousarray(np.asarray(amp, dtype=np.float64))
+            amp_p = a.ctypes.data_as(_lib.P_double)
+        ms = np.zeros(_lib.NPASS)
+        tot = ctypes.c_double()
+        check(self.lib.dgpe_step_profiled(self.handle, _ptr(psi), int(nsteps), amp_p,
+                                          ms.ctypes.data_as(_lib.P_double), ctypes.byref(tot)))
+        return dict(zip(_lib.PASS_NAMES, ms.tolist())), tot.value
+
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.dgpe_plan_destroy(self.handle)

@@ -26,6 +26,8 @@ STATUS_NAMES = {
 DGPE_IMAG, DGPE_REAL, DGPE_F64, DGPE_F32 = 0, 1, 0, 2
 PARAM = {"g": 0, "gd": 1, "nu": 2, "lambda": 3, "gamma": 4, "dt": 5, "real_time": 6}
 OBJECTIVE = {"energy": 0, "overlap": 1}
+NPASS = 8
+PASS_NAMES = ["r2c_z", "fft_y", "fft_x_mul", "ifft_y", "c2r_z_nonlinear_cn_z", "cn_y", "cn_x", "norm_reduce"]
 
 
 class DgpeObs(ctypes.Structure):
@@ -50,6 +52,8 @@ SIGNATURES = {
     "dgpe_step_adjoint": (c_int32, [c_void_p, c_void_p, c_int32, P_double, c_int32, c_int32,
                                     c_void_p, c_void_p, c_size_t, c_void_p, P_double, P_double,
                                     P_double, c_void_p]),
+    "dgpe_pass_bytes": (c_int32, [c_void_p, P_double]),
+    "dgpe_step_profiled": (c_int32, [c_void_p, c_void_p, c_int32, P_double, P_double, P_double]),
     "dgpe_plan_destroy": (None, [c_void_p]),
     "dgpe_status_string": (c_char_p, [c_int32]),
     "dgpe_last_error": (c_char_p, []),

@@ -72,7 +72,7 @@ int ilog2(int v) {
 
 size_t c2r_step_lds(int Nz, int B, size_t csz) {
     const int M = Nz / 2, es = B + 1;
-    return (size_t)((M + 1) * es + Nz * es + M + M + 1) * csz;
+    return (size_t)((M + 1) * es + Nz * es + M + M + 1 + 2 * (Nz / 16 + 1)) * csz;
 }
 
 // Block shapes for a grid; false if no shape fits the LDS budget.
@@ -87,9 +87,9 @@ bool choose_launch(const int n[3], bool f32, Launch* lc) {
     while (Bz > 1 && (Ny % Bz || Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsBudget)) Bz >>= 1;
     if (Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsBudget) return false;
     lc->logB_z = ilog2(Bz);
-    // z segments: B * nseg <= threads
+    // z segments (16 or 32 points): B * nseg <= threads
     int sz = 16;
-    while (sz < 32 && Bz * ((Nz + sz - 1) / sz) > kThreads) sz <<= 1;
+    if (Bz * ((Nz + sz - 1) / sz) > kThreads) sz = 32;
     if (Bz * ((Nz + sz - 1) / sz) > kThreads) return false;
     if (2 * ((Nz + sz - 1) / sz) * Bz > (M + 1) * (Bz + 1)) return false;
     lc->seg[2] = sz;
@@ -104,36 +104,20 @@ bool choose_launch(const int n[3], bool f32, Launch* lc) {
         Bx >>= 1;
     if (Bx * Nx > cap || (size_t)(Nx * (Bx + 1) + Nx) * csz > kLdsBudget) return false;
     lc->logB_x = ilog2(Bx);
-    // strided sweeps: columns C, segments S, ZB | C, nseg * ZB <= 1024
+    // strided sweeps: columns C, segments S, ZB | C; FP32 blocks up to 1024
+    // threads, FP64 up to 512 (register budget of the segment arrays)
     for (int axis = 0; axis < 2; ++axis) {
         const int L = n[axis];
         const int C = axis == 1 ? Nz : Ny * Nz;
-        bool ok = false;
-        const int segs[2] = {16, 32};
-        for (int si = 0; si < 2 && !ok; ++si) {
-            const int S = segs[si];
-            if (!f32 && S == 32 && L <= 512) continue;  // keep FP64 register use low
-            const int nseg = (L + S - 1) / S;
-            for (int zb = 64; zb >= 1; zb >>= 1) {
-                if (C % zb == 0 && nseg * zb <= 1024 && (zb >= 16 || zb == C)) {
-                    lc->seg[axis] = S;
-                    lc->logZB[axis] = ilog2(zb);
-                    ok = true;
-                    break;
-                }
-            }
-        }
-        if (!ok) {
-            // small grids: any power-of-two column block
-            const int S = 16, nseg = (L + S - 1) / S;
-            for (int zb = 64; zb >= 1 && !ok; zb >>= 1)
-                if (C % zb == 0 && nseg * zb <= 1024) {
-                    lc->seg[axis] = S;
-                    lc->logZB[axis] = ilog2(zb);
-                    ok = true;
-                }
-        }
-        if (!ok) return false;
+        const int S = 16;
+        const int nseg = (L + S - 1) / S;
+        const int tmax = f32 ? 1024 : 512;
+        int zb = 64;
+        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * L + 2 * nseg) * csz; };
+        while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
+        if (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget) return false;
+        lc->seg[axis] = S;
+        lc->logZB[axis] = ilog2(zb);
     }
     return true;
 }
@@ -193,34 +177,34 @@ std::vector<T> twiddles(int L, int count) {
     return out;
 }
 
-// Thomas factors of tridiag(-A, 1 + 2A, -A) and the segment carry products.
+// Thomas factors of tridiag(-A, 1 + 2A, -A) and the segment carry products:
+// alpha_i = A m_i with m_0 = 1/(1 + 2A), m_i = 1/(1 + 2A - A^2 m_{i-1}).
 template <typename T>
 std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
     using C = std::complex<long double>;
-    std::vector<C> m(N), al(N), ga(N), P(N), Q(N);
-    const C sub = -A, diag = C(1) + C(2) * A, sup = -A;
-    C cprev = 0;
+    std::vector<C> al(N), P(N), Q(N), pend(N, C(0)), qbeg(N, C(0));
+    const C diag = C(1) + C(2) * A;
+    C m = C(1) / diag;
     for (int i = 0; i < N; ++i) {
-        m[i] = C(1) / (diag - sub * cprev);
-        const C cp = sup * m[i];
-        al[i] = -sub * m[i];
-        ga[i] = -cp;
-        cprev = cp;
+        if (i > 0) m = C(1) / (diag - A * A * m);
+        al[i] = A * m;
     }
-    for (int s0 = 0; s0 < N; s0 += S) {
+    for (int s0 = 0, k = 0; s0 < N; s0 += S, ++k) {
         const int s1 = std::min(s0 + S, N);
         C acc = 1;
         for (int i = s0; i < s1; ++i) { acc *= al[i]; P[i] = acc; }
+        pend[k] = acc;
         acc = 1;
-        for (int i = s1 - 1; i >= s0; --i) { acc *= ga[i]; Q[i] = acc; }
+        for (int i = s1 - 1; i >= s0; --i) { acc *= al[i]; Q[i] = acc; }
+        qbeg[k] = acc;
     }
     std::vector<T> out(2 * TAB_COUNT * (size_t)N);
     const std::vector<C>* tabs[TAB_COUNT];
-    tabs[TAB_M] = &m;
     tabs[TAB_ALPHA] = &al;
-    tabs[TAB_GAMMA] = &ga;
     tabs[TAB_P] = &P;
     tabs[TAB_Q] = &Q;
+    tabs[TAB_PEND] = &pend;
+    tabs[TAB_QBEG] = &qbeg;
     for (int t = 0; t < TAB_COUNT; ++t)
         for (int i = 0; i < N; ++i) {
             out[2 * ((size_t)t * N + i)] = (T)(*tabs[t])[i].real();
@@ -284,22 +268,72 @@ dgpe_status convolve_density(Plan& p, const void* psi, const double* sigma) {
     return DGPE_OK;
 }
 
+// Optional per-pass event pairs (measurement only).
+struct PassTimer {
+    std::vector<hipEvent_t> ev;  // [launch][2]
+    std::vector<int> kind;
+    hipStream_t stream = nullptr;
+    bool on = false;
+    hipError_t begin(int k) {
+        if (!on) return hipSuccess;
+        hipEvent_t a, b;
+        hipError_t e = hipEventCreate(&a);
+        if (e != hipSuccess) return e;
+        if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+        ev.push_back(a);
+        ev.push_back(b);
+        kind.push_back(k);
+        return hipEventRecord(a, stream);
+    }
+    hipError_t end() { return on ? hipEventRecord(ev.back(), stream) : hipSuccess; }
+    ~PassTimer() {
+        for (hipEvent_t e : ev) hipEventDestroy(e);
+    }
+};
+
+#define DGPE_PASS(timer, k, expr)       \
+    do {                                \
+        DGPE_HIP((timer).begin(k));     \
+        DGPE_HIP(expr);                 \
+        DGPE_HIP((timer).end());        \
+    } while (0)
+
 template <typename T>
-dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp) {
+dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTimer* tm = nullptr) {
+    PassTimer none;
+    PassTimer& t = tm ? *tm : none;
     double* sigma = p.scal;
     const int nb_x = cn_strided_blocks(p, 0);
     for (int s = 0; s < nsteps; ++s) {
         const double a = amp ? amp[s] : 1.0;
         const double* sg = (p.imag && s > 0) ? sigma : nullptr;
-        dgpe_status st = convolve_density<T>(p, psi, sg);
-        if (st != DGPE_OK) return st;
-        DGPE_HIP(launch_c2r_step<T>(p, psi, sg, a));
-        DGPE_HIP(launch_cn_strided<T>(p, psi, 1, false, nullptr));
-        DGPE_HIP(launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr));
-        if (p.imag) DGPE_HIP(launch_norm_finalize(p, p.red, nb_x, sigma));
+        DGPE_PASS(t, 0, (launch_r2c_density<T>(p, psi, sg)));
+        DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
+        DGPE_PASS(t, 2, (launch_xmul<T>(p)));
+        DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
+        DGPE_PASS(t, 4, (launch_c2r_step<T>(p, psi, sg, a)));
+        DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
+        DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr)));
+        if (p.imag) DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb_x, sigma)));
     }
     if (p.imag && nsteps > 0) DGPE_HIP(launch_scale<T>(p, psi, sigma));
     return DGPE_OK;
+}
+
+void pass_bytes(const Plan& p, double b[DGPE_NPASS]) {
+    const double s = p.f32 ? 4.0 : 8.0;
+    const double nt = (double)p.n[0] * p.n[1] * p.n[2];
+    const double state = 2.0 * s * nt;
+    const double spec = 2.0 * s * (double)p.n[0] * p.n[1] * (p.n[2] / 2 + 1);
+    const double uk = s * (double)(p.n[0] / 2 + 1) * (p.n[1] / 2 + 1) * (p.n[2] / 2 + 1);
+    b[0] = state + spec;         // read psi, write S
+    b[1] = 2.0 * spec;           // S in place
+    b[2] = 2.0 * spec + uk;      // S in place + kernel table
+    b[3] = 2.0 * spec;
+    b[4] = spec + 2.0 * state;   // read S and psi, write psi
+    b[5] = 2.0 * state;          // psi in place
+    b[6] = 2.0 * state;
+    b[7] = p.imag ? 8.0 * cn_strided_blocks(p, 0) + 8.0 : 0.0;
 }
 
 template <typename T>
@@ -672,6 +706,49 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
                                        psi_final, J, dJ_damp, dJ_dtrap, dJ_dpsi0)
                  : adjoint_impl<double>(p, psi0, nsteps, amp, K, objective, target, (char*)adj_ws,
                                         psi_final, J, dJ_damp, dJ_dtrap, dJ_dpsi0);
+}
+
+dgpe_status dgpe_pass_bytes(dgpe_plan plan, double bytes[DGPE_NPASS]) {
+    if (!plan || !bytes) return fail(DGPE_EINVAL, "plan and bytes must be non-NULL");
+    pass_bytes(*plan, bytes);
+    return DGPE_OK;
+}
+
+dgpe_status dgpe_step_profiled(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp,
+                               double ms[DGPE_NPASS], double* total_ms) {
+    if (!plan || !ms) return fail(DGPE_EINVAL, "plan and ms must be non-NULL");
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    if (nsteps < 0) return fail(DGPE_EINVAL, "nsteps must be >= 0");
+    Plan& p = *plan;
+    PassTimer tm;
+    tm.on = true;
+    tm.stream = p.stream;
+    hipEvent_t t0, t1;
+    DGPE_HIP(hipEventCreate(&t0));
+    DGPE_HIP(hipEventCreate(&t1));
+    DGPE_HIP(hipEventRecord(t0, p.stream));
+    st = p.f32 ? run_steps<float>(p, psi, nsteps, amp, &tm) : run_steps<double>(p, psi, nsteps, amp, &tm);
+    if (st != DGPE_OK) return st;
+    DGPE_HIP(hipEventRecord(t1, p.stream));
+    DGPE_HIP(hipStreamSynchronize(p.stream));
+    double sum[DGPE_NPASS] = {0};
+    int cnt[DGPE_NPASS] = {0};
+    for (size_t i = 0; i < tm.kind.size(); ++i) {
+        float m = 0.f;
+        DGPE_HIP(hipEventElapsedTime(&m, tm.ev[2 * i], tm.ev[2 * i + 1]));
+        sum[tm.kind[i]] += m;
+        cnt[tm.kind[i]] += 1;
+    }
+    for (int k = 0; k < DGPE_NPASS; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+    if (total_ms) {
+        float m = 0.f;
+        DGPE_HIP(hipEventElapsedTime(&m, t0, t1));
+        *total_ms = m;
+    }
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    return DGPE_OK;
 }
 
 void dgpe_plan_destroy(dgpe_plan plan) { delete plan; }

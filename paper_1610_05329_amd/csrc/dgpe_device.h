@@ -217,81 +217,98 @@ namespace dgpe {
 // Crank-Nicolson solve of one line split into segments of S points.
 //
 // (1 - A D) x = (1 + A D) u on a line of N points with zero ghosts is a
-// constant tridiagonal system; its Thomas factors (m, alpha, gamma) depend
-// only on the position, so they are plan tables.  Each thread owns the
-// segment [e0, e0 + cnt) of one line in registers (v, holding u on entry) and
-//   1. forms the right-hand side from its points and the neighbours `left`
-//      (u_{e0-1}) and `right` (u_{e0+cnt}), zero beyond the line;
-//   2. runs forward elimination from a zero carry, publishes its last value;
-//   3. adds P_i * (true d_{e0-1}), where the true value follows from the
-//      published values of the segments to its left (linear recurrence);
-//   4. runs back substitution from a zero carry, publishes its first value,
-//      and adds Q_i * (true x_{e0+cnt}) from the segments to its right.
+// constant tridiagonal system tridiag(-A, 1 + 2A, -A).  Thomas elimination
+// with pivots 1/m_i gives m_0 = 1/(1 + 2A), m_i = 1/(1 + 2A - A^2 m_{i-1});
+// with alpha_i = A m_i both the forward and the backward recurrences use the
+// same factor:
+//   d_i = alpha_i (d_{i-1} + r'_i),  r'_i = u_{i-1} + u_{i+1} + kappa u_i,
+//   kappa = 1/A - 2  (r' is the right-hand side divided by A),
+//   x_i = d_i + alpha_i x_{i+1}.
+// Each thread owns the segment [e0, e0 + cnt) of one line in registers (v,
+// holding u on entry) and
+//   1. forms r' from its points and the neighbours `left` (u_{e0-1}) and
+//      `right` (u_{e0+cnt}), zero beyond the line;
+//   2. runs the forward recurrence from a zero carry, publishes its last d;
+//   3. adds P_i * (true d_{e0-1}), P_i = prod_{j=e0}^{i} alpha_j, where the
+//      true value follows from the published ends of the segments on its left
+//      through d_end(k) = dtilde_end(k) + Pend(k) d_end(k-1);
+//   4. runs back substitution from a zero carry, publishes its first x, and
+//      adds Q_i * (true x_{e0+cnt}), Q_i = prod_{j=i}^{e0+cnt-1} alpha_j.
 // The result equals plain Thomas elimination up to rounding (no truncation).
-// All threads of the block must call this (it contains two barriers);
-// threads without a segment pass cnt = 0.  dl and xf are LDS arrays of
-// nseg * nlines entries, indexed [seg * nlines + line].
+// alpha, P, Q are plan tables (length N); pend/qbeg hold P at each segment's
+// end and Q at each segment's start.  RC: real coefficients (imaginary time).
+// GUARD: segments may be partial (cnt < S); otherwise every active thread has
+// cnt == S.  All threads of the block call this (two barriers); threads
+// without a segment pass cnt = 0.  dl and xf are LDS arrays of nseg * nlines
+// entries, indexed [seg * nlines + line].
 // ---------------------------------------------------------------------------
-template <typename T, int S>
+template <bool RC, typename T>
+__device__ __forceinline__ cx<T> kmul(cx<T> k, cx<T> a) {
+    if constexpr (RC) return cx<T>{k.x * a.x, k.x * a.y};
+    else return cmul(k, a);
+}
+
+template <typename T, int S, bool RC, bool GUARD>
 __device__ __forceinline__ void cn_segment_solve(cx<T> (&v)[S], int cnt, cx<T> left, cx<T> right,
-                                                 cx<T> A, const cx<T>* __restrict__ tab, int N,
-                                                 int e0, int seg, int nseg, cx<T>* dl, cx<T>* xf,
-                                                 int line, int nlines) {
-    const cx<T>* tm = tab + TAB_M * N;
-    const cx<T>* ta = tab + TAB_ALPHA * N;
-    const cx<T>* tg = tab + TAB_GAMMA * N;
-    const cx<T>* tp = tab + TAB_P * N;
-    const cx<T>* tq = tab + TAB_Q * N;
-    const cx<T> diag = {T(1) - T(2) * A.x, -T(2) * A.y};
-    // 1. right-hand side (1 + A D) u
+                                                 cx<T> kappa, const cx<T>* ta, const cx<T>* tp,
+                                                 const cx<T>* tq, const cx<T>* pend,
+                                                 const cx<T>* qbeg, int e0, int seg, int nseg,
+                                                 cx<T>* dl, cx<T>* xf, int line, int nlines) {
+    const bool act = cnt > 0;
+    cx<T> al[S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+        if (act && (!GUARD || i < cnt)) al[i] = ta[e0 + i];
+    // 1. r'_i = u_{i-1} + u_{i+1} + kappa u_i
     cx<T> prev = left;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        if (i < cnt) {
+        if (!GUARD || i < cnt) {
             const cx<T> cur = v[i];
             cx<T> nxt = right;
-            if (i + 1 < S && i + 1 < cnt) nxt = v[(i + 1 < S) ? i + 1 : i];
-            v[i] = cmul(A, prev + nxt) + cmul(diag, cur);
+            if (i + 1 < S) {
+                if (!GUARD || i + 1 < cnt) nxt = v[(i + 1 < S) ? i + 1 : i];
+            }
+            v[i] = prev + nxt + kmul<RC>(kappa, cur);
             prev = cur;
         }
     }
-    // 2. forward elimination with a zero carry
+    // 2. forward recurrence, zero carry
     cx<T> dcur = {T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        if (i < cnt) {
-            const int e = e0 + i;
-            dcur = cmul(ta[e], dcur) + cmul(tm[e], v[i]);
+        if (!GUARD || i < cnt) {
+            dcur = kmul<RC>(al[i], dcur + v[i]);
             v[i] = dcur;
         }
     }
-    if (cnt > 0) dl[seg * nlines + line] = dcur;
+    if (act) dl[seg * nlines + line] = dcur;
     __syncthreads();
-    if (cnt > 0) {
+    if (act) {
         // 3. true d_{e0-1} from the segments on the left
         cx<T> c = {T(0), T(0)};
-        for (int k = 0; k < seg; ++k) c = dl[k * nlines + line] + cmul(tp[k * S + S - 1], c);
+        for (int k = 0; k < seg; ++k) c = dl[k * nlines + line] + kmul<RC>(pend[k], c);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (i < cnt) v[i] = v[i] + cmul(tp[e0 + i], c);
-        // 4. back substitution with a zero carry
+            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(tp[e0 + i], c);
+        // 4. back substitution, zero carry
         cx<T> xcur = {T(0), T(0)};
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
-            if (i < cnt) {
-                xcur = v[i] + cmul(tg[e0 + i], xcur);
+            if (!GUARD || i < cnt) {
+                xcur = v[i] + kmul<RC>(al[i], xcur);
                 v[i] = xcur;
             }
         }
         xf[seg * nlines + line] = xcur;
     }
     __syncthreads();
-    if (cnt > 0) {
+    if (act) {
         cx<T> c = {T(0), T(0)};
-        for (int k = nseg - 1; k > seg; --k) c = xf[k * nlines + line] + cmul(tq[k * S], c);
+        for (int k = nseg - 1; k > seg; --k) c = xf[k * nlines + line] + kmul<RC>(qbeg[k], c);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (i < cnt) v[i] = v[i] + cmul(tq[e0 + i], c);
+            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(tq[e0 + i], c);
     }
 }
 

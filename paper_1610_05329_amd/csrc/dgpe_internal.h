@@ -23,12 +23,11 @@ struct FastDiv {
 };
 
 // Per-axis Crank-Nicolson tables (complex, plan precision), each of length N,
-// stored back to back: for (1 - A D) x = (1 + A D) u with zero ghosts,
-//   d_i = alpha_i d_{i-1} + m_i r_i            (forward elimination)
-//   x_i = d_i + gamma_i x_{i+1}                (back substitution)
-// and, for segments of S points, the carry products
-//   P_i = prod_{j = seg start}^{i} alpha_j,  Q_i = prod_{j = i}^{seg end - 1} gamma_j.
-enum { TAB_M = 0, TAB_ALPHA = 1, TAB_GAMMA = 2, TAB_P = 3, TAB_Q = 4, TAB_COUNT = 5 };
+// stored back to back, for (1 - A D) x = (1 + A D) u with zero ghosts:
+//   alpha_i = A m_i with Thomas pivots m_0 = 1/(1 + 2A), m_i = 1/(1 + 2A - A^2 m_{i-1})
+//   P_i = prod_{j = seg start}^{i} alpha_j,  Q_i = prod_{j = i}^{seg end - 1} alpha_j
+//   PEND[k] = P at the last point of segment k, QBEG[k] = Q at its first point.
+enum { TAB_ALPHA = 0, TAB_P = 1, TAB_Q = 2, TAB_PEND = 3, TAB_QBEG = 4, TAB_COUNT = 5 };
 
 // Launch parameters of the seven passes for one plan (host side).
 struct Launch {
@@ -115,6 +114,12 @@ hipError_t launch_reduce(const Plan& p, const double* partials, int nblocks, int
 hipError_t launch_norm_finalize(const Plan& p, const double* partials, int nblocks, double* sigma);
 
 int cn_strided_blocks(const Plan& p, int axis);
+
+// kappa = 1/A - 2 of the scaled Crank-Nicolson right-hand side (conj(A) for the adjoint)
+struct cx_coef {
+    double re, im;
+};
+cx_coef cn_kappa(const Plan& p, int axis, bool conjugate);
 int observables_blocks(const Plan& p);
 int r2c_blocks(const Plan& p);
 

@@ -15,16 +15,48 @@ namespace {
 
 constexpr int kMaxThreads = 1024;
 
-template <typename T, int S>
-__global__ void __launch_bounds__(kMaxThreads)
-    k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg,
-                 const cx<T>* __restrict__ tab, cx<T> A, double* __restrict__ norm_partials) {
-    __shared__ cx<T> s_first[kMaxThreads];
-    __shared__ cx<T> s_last[kMaxThreads];
-    __shared__ cx<T> s_dl[kMaxThreads];
+template <typename T>
+struct CnTab {
+    const cx<T>* a;
+    const cx<T>* p;
+    const cx<T>* q;
+    const cx<T>* pend;
+    const cx<T>* qbeg;
+};
+
+template <typename T>
+CnTab<T> tab_of(const void* base, int N) {
+    const cx<T>* t = (const cx<T>*)base;
+    return CnTab<T>{t + TAB_ALPHA * N, t + TAB_P * N, t + TAB_Q * N, t + TAB_PEND * N,
+                    t + TAB_QBEG * N};
+}
+
+// LDS: A1[nseg*ZB] | A2[nseg*ZB] | alpha[L] | P[L] | Q[L] | pend[nseg] | qbeg[nseg]
+template <typename T, int S, bool RC, bool GUARD>
+__global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads)
+    k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab<T> tg,
+                 cx<T> kappa, double* __restrict__ norm_partials) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_red[kMaxThreads / 64];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nthr = blockDim.x;
     const int ZB = 1 << logZB;
+    const int nsl = nseg << logZB;
+    cx<T>* A1 = reinterpret_cast<cx<T>*>(smem_raw);
+    cx<T>* A2 = A1 + nsl;
+    cx<T>* ta = A2 + nsl;
+    cx<T>* tp = ta + L;
+    cx<T>* tq = tp + L;
+    cx<T>* pe = tq + L;
+    cx<T>* qb = pe + nseg;
+    for (int i = tid; i < L; i += nthr) {
+        ta[i] = tg.a[i];
+        tp[i] = tg.p[i];
+        tq[i] = tg.q[i];
+    }
+    for (int i = tid; i < nseg; i += nthr) {
+        pe[i] = tg.pend[i];
+        qb[i] = tg.qbeg[i];
+    }
     const int ncb = C >> logZB;
     const int o = blockIdx.x / ncb;
     const int c0 = (blockIdx.x - o * ncb) << logZB;
@@ -34,30 +66,32 @@ __global__ void __launch_bounds__(kMaxThreads)
     const int cnt = (seg < nseg) ? min(S, L - e0) : 0;
     cx<T>* base = f + (size_t)o * L * C + c0 + cl;
     cx<T> v[S];
-    cx<T> lastv = {T(0), T(0)};
 #pragma unroll
     for (int i = 0; i < S; ++i)
-        if (i < cnt) v[i] = base[(size_t)(e0 + i) * C];
+        if (!GUARD || i < cnt) v[i] = base[(size_t)(e0 + i) * C];
+    cx<T> lastv = v[S - 1];
+    if (GUARD) {
 #pragma unroll
-    for (int i = 0; i < S; ++i)
-        if (i == cnt - 1) lastv = v[i];
+        for (int i = 0; i < S; ++i)
+            if (i == cnt - 1) lastv = v[i];
+    }
     if (cnt > 0) {
-        s_first[seg * ZB + cl] = v[0];
-        s_last[seg * ZB + cl] = lastv;
+        A1[seg * ZB + cl] = v[0];
+        A2[seg * ZB + cl] = lastv;
     }
     __syncthreads();
     cx<T> left = {T(0), T(0)}, right = {T(0), T(0)};
     if (cnt > 0) {
-        if (seg > 0) left = s_last[(seg - 1) * ZB + cl];
-        if (seg + 1 < nseg) right = s_first[(seg + 1) * ZB + cl];
+        if (seg > 0) left = A2[(seg - 1) * ZB + cl];
+        if (seg + 1 < nseg) right = A1[(seg + 1) * ZB + cl];
     }
-    // s_first is only rewritten (as the backward carries) after the solver's
-    // first barrier, by which time every neighbour read above has completed.
-    cn_segment_solve<T, S>(v, cnt, left, right, A, tab, L, e0, seg, nseg, s_dl, s_first, cl, ZB);
+    __syncthreads();  // neighbour reads done: A2 becomes the forward carries, A1 the backward ones
+    cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta + 0, tp, tq, pe, qb, e0, seg,
+                                      nseg, A2, A1, cl, ZB);
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        if (i < cnt) {
+        if (!GUARD || i < cnt) {
             base[(size_t)(e0 + i) * C] = v[i];
             acc += double(abs2(v[i]));
         }
@@ -69,9 +103,9 @@ __global__ void __launch_bounds__(kMaxThreads)
 }
 
 // Standalone z sweep of B = 2^logB contiguous lines, staged through LDS.
-template <typename T, int SZ>
+template <typename T, int SZ, bool RC, bool GUARD>
 __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int logB, int ES,
-                                             const cx<T>* __restrict__ tab, cx<T> A) {
+                                             CnTab<T> tg, cx<T> kappa) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* P = reinterpret_cast<cx<T>*>(smem_raw);
     const int B = 1 << logB;
@@ -95,15 +129,16 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (i < cnt) v[i] = P[(e0 + i) * ES + bl];
+            if (!GUARD || i < cnt) v[i] = P[(e0 + i) * ES + bl];
         if (e0 > 0) left = P[(e0 - 1) * ES + bl];
         if (e0 + cnt < Nz) right = P[(e0 + cnt) * ES + bl];
     }
-    cn_segment_solve<T, SZ>(v, cnt, left, right, A, tab, Nz, e0, seg, nseg, dl, xf, bl, B);
+    cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, tg.a, tg.p, tg.q, tg.pend,
+                                       tg.qbeg, e0, seg, nseg, dl, xf, bl, B);
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (i < cnt) P[(e0 + i) * ES + bl] = v[i];
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = v[i];
     }
     __syncthreads();
     for (int g = tid; g < total; g += nthr) {
@@ -112,14 +147,14 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
     }
 }
 
-template <typename T>
-cx<T> cn_coef(const Plan& p, int axis, bool conjugate) {
-    const double a = p.dt / (4.0 * p.d[axis] * p.d[axis]);
-    if (p.imag) return cx<T>{T(a), T(0)};
-    return cx<T>{T(0), T(conjugate ? -a : a)};
-}
-
 }  // namespace
+
+cx_coef cn_kappa(const Plan& p, int axis, bool conjugate) {
+    // kappa = 1/A - 2 with A = dt/(4 d^2) (imaginary time) or +-i dt/(4 d^2)
+    const double a = p.dt / (4.0 * p.d[axis] * p.d[axis]);
+    if (p.imag) return cx_coef{1.0 / a - 2.0, 0.0};
+    return cx_coef{-2.0, conjugate ? 1.0 / a : -1.0 / a};
+}
 
 int cn_strided_blocks(const Plan& p, int axis) {
     const int zb = 1 << p.lc.logZB[axis];
@@ -136,16 +171,26 @@ hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
     const int logZB = p.lc.logZB[axis];
     const int nseg = (L + S - 1) / S;
     const int threads = nseg << logZB;
-    const cx<T>* tab = (const cx<T>*)p.cntab[axis][conjugate ? 1 : 0];
-    const cx<T> A = cn_coef<T>(p, axis, conjugate);
+    const CnTab<T> tg = tab_of<T>(p.cntab[axis][conjugate ? 1 : 0], L);
+    const cx_coef k = cn_kappa(p, axis, conjugate);
+    const cx<T> kappa = {T(k.re), T(k.im)};
     const int blocks = cn_strided_blocks(p, axis);
-#define DGPE_CN(SV)                                                                               \
-    hipLaunchKernelGGL((k_cn_strided<T, SV>), dim3(blocks), dim3(threads), 0, p.stream, (cx<T>*)f, \
-                       L, C, logZB, nseg, tab, A, norm_partials)
-    if (S == 8) DGPE_CN(8);
-    else if (S == 16) DGPE_CN(16);
-    else if (S == 32) DGPE_CN(32);
+    const size_t sm = (size_t)(2 * threads + 3 * L + 2 * nseg) * sizeof(cx<T>);
+    const bool guard = (L % S) != 0;
+#define DGPE_CN(SV, RCV, GV)                                                                      \
+    hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV>), dim3(blocks), dim3(threads), sm, p.stream, \
+                       (cx<T>*)f, L, C, logZB, nseg, tg, kappa, norm_partials)
+#define DGPE_CN_S(SV)                           \
+    if (p.imag) {                               \
+        if (guard) DGPE_CN(SV, true, true);     \
+        else DGPE_CN(SV, true, false);          \
+    } else {                                    \
+        if (guard) DGPE_CN(SV, false, true);    \
+        else DGPE_CN(SV, false, false);         \
+    }
+    if (S == 16) { DGPE_CN_S(16) }
     else return hipErrorInvalidValue;
+#undef DGPE_CN_S
 #undef DGPE_CN
     return hipGetLastError();
 }
@@ -160,15 +205,25 @@ hipError_t launch_cn_z(const Plan& p, void* f, bool conjugate) {
     const int nseg = (Nz + S - 1) / S;
     const size_t sm = (size_t)(Nz * es + 2 * nseg * B) * sizeof(cx<T>);
     const int blocks = (p.n[0] * p.n[1]) >> logB;
-    const cx<T>* tab = (const cx<T>*)p.cntab[2][conjugate ? 1 : 0];
-    const cx<T> A = cn_coef<T>(p, 2, conjugate);
-#define DGPE_CNZ(SV)                                                                             \
-    hipLaunchKernelGGL((k_cn_z<T, SV>), dim3(blocks), dim3(p.lc.threads), sm, p.stream, (cx<T>*)f, \
-                       Nz, logB, es, tab, A)
-    if (S == 8) DGPE_CNZ(8);
-    else if (S == 16) DGPE_CNZ(16);
-    else if (S == 32) DGPE_CNZ(32);
+    const CnTab<T> tg = tab_of<T>(p.cntab[2][conjugate ? 1 : 0], Nz);
+    const cx_coef k = cn_kappa(p, 2, conjugate);
+    const cx<T> kappa = {T(k.re), T(k.im)};
+    const bool guard = (Nz % S) != 0;
+#define DGPE_CNZ(SV, RCV, GV)                                                                     \
+    hipLaunchKernelGGL((k_cn_z<T, SV, RCV, GV>), dim3(blocks), dim3(p.lc.threads), sm, p.stream, \
+                       (cx<T>*)f, Nz, logB, es, tg, kappa)
+#define DGPE_CNZ_S(SV)                          \
+    if (p.imag) {                               \
+        if (guard) DGPE_CNZ(SV, true, true);    \
+        else DGPE_CNZ(SV, true, false);         \
+    } else {                                    \
+        if (guard) DGPE_CNZ(SV, false, true);   \
+        else DGPE_CNZ(SV, false, false);        \
+    }
+    if (S == 16) { DGPE_CNZ_S(16) }
+    else if (S == 32) { DGPE_CNZ_S(32) }
     else return hipErrorInvalidValue;
+#undef DGPE_CNZ_S
 #undef DGPE_CNZ
     return hipGetLastError();
 }

@@ -334,28 +334,35 @@ __device__ __forceinline__ void c2r_front(cx<T>* buf, cx<T>* stw, cx<T>* sr2c,
 }
 
 // P5: z inverse transform -> Phi, nonlinear phase, Crank-Nicolson along z.
-// LDS: F (M+1 rows) | Psi (Nz rows) | twiddles | carries.
-template <typename T, int SZ>
+// LDS: F (M+1 rows) | Psi (Nz rows) | twiddles | segment carry products.
+template <typename T, int SZ, bool RC, bool GUARD>
 __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
                                                  const cx<T>* __restrict__ spec, int Nx, int Ny,
                                                  int Nz, int logB, int ES, FftDesc fz,
                                                  const cx<T>* __restrict__ twz,
                                                  const cx<T>* __restrict__ twr2c,
-                                                 const cx<T>* __restrict__ cntab, cx<T> A,
+                                                 const cx<T>* __restrict__ cntab, cx<T> kappa,
                                                  const double* __restrict__ sigma, TrapGeo geo,
                                                  Phys ph) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int M = Nz >> 1;
+    const int nseg = (Nz + SZ - 1) / SZ;
     cx<T>* F = reinterpret_cast<cx<T>*>(smem_raw);
     cx<T>* P = F + (M + 1) * ES;
     cx<T>* stw = P + Nz * ES;
     cx<T>* sr2c = stw + M;
+    cx<T>* spe = sr2c + M + 1;
+    cx<T>* sqb = spe + nseg;
     const int B = 1 << logB;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ngy = Ny >> logB;
     const int x = blockIdx.x / ngy;
     const int y0 = (blockIdx.x - x * ngy) << logB;
     const size_t line0 = (size_t)x * Ny + y0;
+    for (int i = tid; i < nseg; i += nthr) {
+        spe[i] = cntab[TAB_PEND * Nz + i];
+        sqb[i] = cntab[TAB_QBEG * Nz + i];
+    }
     c2r_front<T>(F, stw, sr2c, spec, twz, twr2c, Nx, Ny, M, logB, ES, fz, line0);
 
     // nonlinear step on the B lines (pre-step density, lazily normalised)
@@ -398,7 +405,6 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     __syncthreads();
 
     // Crank-Nicolson along z: thread -> (line b, segment s)
-    const int nseg = (Nz + SZ - 1) / SZ;
     cx<T>* dl = F;  // F is dead now; carries reuse it
     cx<T>* xf = F + nseg * B;
     const int bl = tid & (B - 1);
@@ -410,16 +416,18 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (i < cnt) v[i] = P[(e0 + i) * ES + bl];
+            if (!GUARD || i < cnt) v[i] = P[(e0 + i) * ES + bl];
         if (e0 > 0) left = P[(e0 - 1) * ES + bl];
         if (e0 + cnt < Nz) right = P[(e0 + cnt) * ES + bl];
     }
-    cn_segment_solve<T, SZ>(v, cnt, left, right, A, cntab, Nz, e0, seg, nseg, dl, xf, bl, B);
+    cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, cntab + TAB_ALPHA * Nz,
+                                       cntab + TAB_P * Nz, cntab + TAB_Q * Nz, spe, sqb, e0, seg,
+                                       nseg, dl, xf, bl, B);
     // cn_segment_solve ended with a barrier after every neighbour read
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (i < cnt) P[(e0 + i) * ES + bl] = v[i];
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = v[i];
     }
     __syncthreads();
     for (int g = tid; g < total; g += nthr) {
@@ -492,7 +500,8 @@ inline size_t sm_r2c(const Plan& p, int es, size_t csz) {
 }
 inline size_t sm_c2r_step(const Plan& p, int es, size_t csz) {
     const int M = p.n[2] / 2;
-    return (size_t)((M + 1) * es + p.n[2] * es + M + M + 1) * csz;
+    const int nseg = (p.n[2] + p.lc.seg[2] - 1) / p.lc.seg[2];
+    return (size_t)((M + 1) * es + p.n[2] * es + M + M + 1 + 2 * nseg) * csz;
 }
 inline size_t sm_c2r_phi(const Plan& p, int es, size_t csz) {
     const int M = p.n[2] / 2;
@@ -564,20 +573,29 @@ template <typename T>
 hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
-    const double a = p.dt / (4.0 * p.d[2] * p.d[2]);
-    cx<T> A = p.imag ? cx<T>{T(a), T(0)} : cx<T>{T(0), T(a)};
+    const cx_coef k = cn_kappa(p, 2, false);
+    const cx<T> kappa = {T(k.re), T(k.im)};
     Phys ph{p.dt, p.g, p.gd, amp, p.imag ? 1 : 0};
     const cx<T>* tab = (const cx<T>*)p.cntab[2][0];
     const int S = p.lc.seg[2];
-#define DGPE_C2R_STEP(SZV)                                                                        \
-    hipLaunchKernelGGL((k_c2r_step<T, SZV>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm, p.stream, \
-                       (cx<T>*)psi, (const cx<T>*)p.spec, p.n[0], p.n[1], p.n[2], p.lc.logB_z, es, \
-                       p.fz, (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, tab, A, sigma,        \
-                       make_geo(p), ph)
-    if (S == 8) DGPE_C2R_STEP(8);
-    else if (S == 16) DGPE_C2R_STEP(16);
-    else if (S == 32) DGPE_C2R_STEP(32);
+    const bool guard = (p.n[2] % S) != 0;
+#define DGPE_C2R_STEP(SZV, RCV, GV)                                                                \
+    hipLaunchKernelGGL((k_c2r_step<T, SZV, RCV, GV>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm, \
+                       p.stream, (cx<T>*)psi, (const cx<T>*)p.spec, p.n[0], p.n[1], p.n[2],         \
+                       p.lc.logB_z, es, p.fz, (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, tab,    \
+                       kappa, sigma, make_geo(p), ph)
+#define DGPE_C2R_S(SZV)                              \
+    if (p.imag) {                                    \
+        if (guard) DGPE_C2R_STEP(SZV, true, true);   \
+        else DGPE_C2R_STEP(SZV, true, false);        \
+    } else {                                         \
+        if (guard) DGPE_C2R_STEP(SZV, false, true);  \
+        else DGPE_C2R_STEP(SZV, false, false);       \
+    }
+    if (S == 16) { DGPE_C2R_S(16) }
+    else if (S == 32) { DGPE_C2R_S(32) }
     else return hipErrorInvalidValue;
+#undef DGPE_C2R_S
 #undef DGPE_C2R_STEP
     return hipGetLastError();
 }

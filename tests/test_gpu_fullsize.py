@@ -1,0 +1,172 @@
+"""Full-size workloads on the GPU against the FP64 oracle's stored records
+(tests/golden/make_fullsize_golden.py), in the launch configuration the
+benchmark uses, plus finite-difference checks of the adjoint.
+
+The stored records hold 512 sampled state values per workload; the GPU state is
+compared at those points (max |error| / max |psi|) and on the observables.
+Each side prepares its own initial state from the same seeded input.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _golden(name):
+    return json.load(open(os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")))
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1610_05329_amd as dg
+    assert torch.cuda.is_available()
+    dg.load()
+    return torch, dg
+
+
+def _sample_err(psi, smp):
+    flat = psi.reshape(-1).cpu().numpy().astype(np.complex128)
+    idx = np.asarray(smp["index"])
+    ref = np.asarray(smp["re"]) + 1j * np.asarray(smp["im"])
+    return float(np.max(np.abs(flat[idx] - ref)) / smp["max_abs"])
+
+
+def _dtype(torch, prec):
+    return torch.complex128 if prec == "f64" else torch.complex64
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c3_256cubed_imaginary_time(env, prec):
+    """256^3 imaginary time, 20 steps (the benchmark's plan shape)."""
+    torch, dg = env
+    cfg = W.CONFIGS["C3"]
+    gold = _golden("c3")
+    _say(f"C3 {prec}: preparing")
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, dtype=_dtype(torch, prec))
+    psi = plan.new_state(W.noisy_gaussian(cfg))
+    plan.step(psi, gold["steps"])
+    err = _sample_err(psi, gold["samples"])
+    o = plan.observables(psi)
+    g = gold["observables"]
+    emu = abs(o["mu"] - g["mu"]) / abs(g["mu"])
+    een = abs(o["energy"] - g["energy"]) / abs(g["energy"])
+    _say(f"C3 {prec}: sampled state err {err:.3e}, mu rel err {emu:.3e}, energy rel err {een:.3e}")
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert err < tol
+    assert emu < tol and een < tol
+    assert abs(o["norm"] - 1.0) < (1e-13 if prec == "f64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c2_128cubed_quench_real_time(env, prec):
+    """128^3: 200 imaginary-time steps at gd = 15, quench to gd = 20, 1000
+    real-time steps; norm conservation and energy drift per dtype."""
+    torch, dg = env
+    cfg = W.CONFIGS["C2"]
+    gold = _golden("c2")
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, gold["prep_gd"], dtype=_dtype(torch, prec))
+    psi = plan.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
+    plan.step(psi, gold["prep_imag_steps"])
+    plan.set("gd", cfg.gd)
+    plan.set("real_time", 1)
+    o0 = plan.observables(psi)
+    plan.step(psi, gold["steps"])
+    o1 = plan.observables(psi)
+    err = _sample_err(psi, gold["samples"])
+    g0, g1 = gold["observables_start"], gold["observables"]
+    drift = o1["energy"] - o0["energy"]
+    gdrift = g1["energy"] - g0["energy"]
+    _say(f"C2 {prec}: sampled state err {err:.3e}; norm drift {o1['norm'] - o0['norm']:.3e}; "
+         f"energy {o0['energy']:.12f} -> {o1['energy']:.12f} (drift {drift:.3e}, oracle {gdrift:.3e})")
+    assert abs(o0["energy"] - g0["energy"]) < (1e-11 if prec == "f64" else 1e-5) * abs(g0["energy"])
+    if prec == "f64":
+        assert err < 1e-12
+        assert abs(o1["norm"] - o0["norm"]) < 1e-12
+        assert abs(drift - gdrift) < 1e-10 * abs(g0["energy"])
+    else:
+        assert err < 1e-4
+        assert abs(o1["norm"] - o0["norm"]) < 1e-5
+        assert abs(drift - gdrift) < 1e-5 * abs(g0["energy"])
+
+
+def _c4_setup(torch, dg, prec, gold):
+    cfg = W.CONFIGS["C4"]
+    prep = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, dtype=_dtype(torch, prec))
+    psi0 = prep.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
+    prep.step(psi0, gold["prep_imag_steps"])
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=_dtype(torch, prec))
+    return cfg, plan, psi0
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_c4_adjoint_matches_oracle(env, prec):
+    torch, dg = env
+    gold = _golden("c4")
+    cfg, plan, psi0 = _c4_setup(torch, dg, prec, gold)
+    W_ = dg.knot_matrix(len(gold["knots"]), gold["steps"], cfg.dt)
+    amp = W_ @ np.asarray(gold["knots"])
+    assert np.max(np.abs(amp - np.asarray(gold["amp"]))) < 1e-14
+    out = plan.adjoint(psi0, amp, ckpt_every=20)
+    dJ = np.asarray(gold["dJ_damp"])
+    e_J = abs(out["J"] - gold["J"]) / abs(gold["J"])
+    e_a = np.max(np.abs(out["dJ_damp"] - dJ)) / np.max(np.abs(dJ))
+    e_t = np.max(np.abs(out["dJ_dtrap"] - np.asarray(gold["dJ_dtrap"]))) / np.max(np.abs(gold["dJ_dtrap"]))
+    e_psi = _sample_err(out["psi_final"], gold["samples_psiN"])
+    e_lam = _sample_err(out["dJ_dpsi0"], gold["samples_lam0"])
+    _say(f"C4 adjoint {prec}: J {e_J:.2e}, dJ/da {e_a:.2e}, dJ/dtrap {e_t:.2e}, psi_N {e_psi:.2e}, lam0 {e_lam:.2e}")
+    tol = 1e-9 if prec == "f64" else 2e-3
+    assert e_J < tol and e_a < tol and e_t < tol and e_lam < tol
+    assert e_psi < (1e-11 if prec == "f64" else 1e-4)
+
+
+def test_c4_adjoint_against_finite_differences(env):
+    """Knot and (lambda, gamma) gradients through DgpeEvolve (FP64) against
+    central differences h = 1e-4 of the GPU forward run: max |g - fd| /
+    max |fd| <= 1e-4."""
+    torch, dg = env
+    gold = _golden("c4")
+    cfg, plan, psi0 = _c4_setup(torch, dg, "f64", gold)
+    nsteps = gold["steps"]
+    knots = torch.tensor(gold["knots"], dtype=torch.float64, requires_grad=True)
+    lg = torch.tensor([cfg.trap[1], cfg.trap[2]], dtype=torch.float64, requires_grad=True)
+    J = dg.DgpeEvolve.apply(knots, lg, psi0, plan, nsteps, 20, "energy", None)
+    J.backward()
+    gk, gt = knots.grad.numpy(), lg.grad.numpy()
+    W_ = dg.knot_matrix(len(gold["knots"]), nsteps, cfg.dt)
+
+    def forward(kn, lam, gam):
+        plan.set("lambda", lam)
+        plan.set("gamma", gam)
+        amp = W_ @ kn
+        psi = psi0.clone()
+        plan.step(psi, nsteps, amp[:-1])
+        o = plan.observables(psi, amp[-1])
+        return o["e_kin"] + o["e_trap"] + o["e_contact"] + o["e_dd"]
+
+    k0 = np.asarray(gold["knots"])
+    h = 1e-4
+    fd = np.zeros(len(k0))
+    for i in range(len(k0)):
+        kp, km = k0.copy(), k0.copy()
+        kp[i] += h
+        km[i] -= h
+        fd[i] = (forward(kp, cfg.trap[1], cfg.trap[2]) - forward(km, cfg.trap[1], cfg.trap[2])) / (2 * h)
+    fdl = (forward(k0, cfg.trap[1] + h, cfg.trap[2]) - forward(k0, cfg.trap[1] - h, cfg.trap[2])) / (2 * h)
+    fdg = (forward(k0, cfg.trap[1], cfg.trap[2] + h) - forward(k0, cfg.trap[1], cfg.trap[2] - h)) / (2 * h)
+    ek = np.max(np.abs(gk - fd)) / np.max(np.abs(fd))
+    et = max(abs(gt[0] - fdl) / abs(fdl), abs(gt[1] - fdg) / abs(fdg))
+    _say(f"C4 FD check: knots {ek:.2e}, (lambda, gamma) {et:.2e}; |dJ/dknots| max {np.max(np.abs(fd)):.3e}")
+    assert abs(float(J) - gold["J"]) < 1e-9 * abs(gold["J"])
+    assert ek < 1e-4 and et < 1e-4
