@@ -70,13 +70,15 @@ int ilog2(int v) {
     return l;
 }
 
+// upper bound of the fused z pass's LDS (16-point segments, FP64 carries)
 size_t c2r_step_lds(int Nz, int B, size_t csz) {
-    const int M = Nz / 2, es = B + 1;
-    return (size_t)((M + 1) * es + Nz * es + M + M + 1 + 2 * (Nz / 16 + 1)) * csz;
+    const int M = Nz / 2, es = B + 1, nseg = (Nz + 15) / 16;
+    const size_t fcap = std::max<size_t>((size_t)(M + 1) * es, ((size_t)2 * nseg * B * 16 + csz - 1) / csz);
+    return (fcap + (size_t)Nz * es + M + M + 1) * csz + 16 + (size_t)2 * nseg * 16;
 }
 
 // Block shapes for a grid; false if no shape fits the LDS budget.
-bool choose_launch(const int n[3], bool f32, Launch* lc) {
+bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
     const size_t csz = f32 ? 8 : 16;
     lc->threads = kThreads;
     const int cap = kEmax * kThreads;
@@ -91,7 +93,6 @@ bool choose_launch(const int n[3], bool f32, Launch* lc) {
     int sz = 16;
     if (Bz * ((Nz + sz - 1) / sz) > kThreads) sz = 32;
     if (Bz * ((Nz + sz - 1) / sz) > kThreads) return false;
-    if (2 * ((Nz + sz - 1) / sz) * Bz > (M + 1) * (Bz + 1)) return false;
     lc->seg[2] = sz;
     // y rows
     int By = f32 ? 16 : 8;
@@ -111,9 +112,13 @@ bool choose_launch(const int n[3], bool f32, Launch* lc) {
         const int C = axis == 1 ? Nz : Ny * Nz;
         const int S = 16;
         const int nseg = (L + S - 1) / S;
-        const int tmax = f32 ? 1024 : 512;
+        // FP32 imaginary time keeps FP32 recurrences (1024-thread blocks); FP64
+        // and real-time recurrences are FP64 (512-thread blocks)
+        const bool narrow = f32 && imag;
+        const int tmax = narrow ? 1024 : 512;
+        const size_t asz = narrow ? 8 : 16;
         int zb = 64;
-        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * L + 2 * nseg) * csz; };
+        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * L + 2 * nseg) * asz; };
         while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
         if (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget) return false;
         lc->seg[axis] = S;
@@ -137,9 +142,12 @@ size_t red_count_for(const int n[3], const Launch& lc) {
 }
 
 // Computes the workspace carve-up; offs[OFF_END] is the total.
-bool layout(const int n[3], bool f32, size_t offs[OFF_END + 1], Launch* lc_out) {
+bool layout(const int n[3], bool f32, size_t offs[OFF_END + 1], Launch* lc_out,
+            bool imag = true) {
     Launch lc;
-    if (!choose_launch(n, f32, &lc)) return false;
+    if (!choose_launch(n, f32, imag, &lc)) return false;
+    Launch other;  // the workspace serves both time modes (dgpe_plan_set)
+    if (!choose_launch(n, f32, !imag, &other)) return false;
     if (lc_out) *lc_out = lc;
     const size_t csz = f32 ? 8 : 16, rsz = f32 ? 4 : 8;
     const size_t nx = n[0], ny = n[1], nz = n[2];
@@ -152,7 +160,7 @@ bool layout(const int n[3], bool f32, size_t offs[OFF_END + 1], Launch* lc_out) 
     sz[OFF_TWZ] = (nz / 2) * csz;
     sz[OFF_TWR] = (nz / 2 + 1) * csz;
     for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 2; ++c) sz[OFF_CN0 + 2 * a + c] = TAB_COUNT * (size_t)n[a] * csz;
+        for (int c = 0; c < 2; ++c) sz[OFF_CN0 + 2 * a + c] = TAB_COUNT * (size_t)n[a] * 16;
     sz[OFF_RED] = red_count_for(n, lc) * sizeof(double);
     sz[OFF_SCAL] = 16 * sizeof(double);
     size_t o = 0;
@@ -226,7 +234,7 @@ dgpe_status build_cn_tables(Plan& p) {
         for (int cj = 0; cj < 2; ++cj) {
             std::complex<long double> A = p.imag ? std::complex<long double>(c, 0)
                                                  : std::complex<long double>(0, cj ? -c : c);
-            dgpe_status s = upload(p.cntab[a][cj], cn_tables<T>(p.n[a], A, p.lc.seg[a]));
+            dgpe_status s = upload(p.cntab[a][cj], cn_tables<double>(p.n[a], A, p.lc.seg[a]));
             if (s != DGPE_OK) return s;
         }
     }
@@ -558,7 +566,7 @@ dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[
     int nn[3] = {n[0], n[1], n[2]};
     size_t offs[OFF_END + 1];
     Launch lc;
-    if (!layout(nn, f32, offs, &lc))
+    if (!layout(nn, f32, offs, &lc, (mode & DGPE_REAL) == 0))
         return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape fits this grid");
     dgpe_status st = check_ptr(workspace, "workspace");
     if (st != DGPE_OK) return fail(DGPE_EWORKSPACE, dgpe_last_error());
@@ -622,10 +630,15 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
             if (!(value > 0)) return fail(DGPE_EINVAL, "dt must be > 0");
             p.dt = value;
             break;
-        case DGPE_PARAM_REAL_TIME:
+        case DGPE_PARAM_REAL_TIME: {
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "REAL_TIME takes 0 or 1");
+            Launch lc;
+            if (!choose_launch(p.n, p.f32, value == 0.0, &lc))
+                return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape for this mode");
             p.imag = value == 0.0;
+            p.lc = lc;
             break;
+        }
         default: return fail(DGPE_EINVAL, "unknown parameter");
     }
     DGPE_HIP(hipStreamSynchronize(p.stream));

@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dgpe_internal.h"
 
 namespace dgpe {
@@ -127,7 +129,7 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
 // Each thread owns at most MAXB butterflies (the launch guarantees it).
 // ---------------------------------------------------------------------------
 template <typename T, int R, bool INV, int MAXB>
-__device__ __forceinline__ void fft_stage(cx<T>* buf, int ES, int L, int logB, int Ns,
+__device__ __forceinline__ void fft_stage(cx<T>* buf, int ES, int L, int logB, int Ns, int logNs,
                                           const cx<T>* tw, int tid, int nthr) {
     const int LR = L / R;
     const int nb = LR << logB;
@@ -141,7 +143,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int ES, int L, int logB, i
         if (t < nb) {
             const int b = t & bmask;
             const int j = t >> logB;
-            const int k = j % Ns;
+            const int k = logNs >= 0 ? (j & (Ns - 1)) : j % Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * LR) * ES + b];
             if (k != 0) {
@@ -174,14 +176,16 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, int ES, int L, int logB, i
 template <typename T, bool INV, int EMAX>
 __device__ __forceinline__ void lds_fft(cx<T>* buf, int ES, const FftDesc& f, int logB,
                                         const cx<T>* tw, int tid, int nthr) {
-    int Ns = 1;
+    int Ns = 1, logNs = 0;
     for (int s = 0; s < f.nstages; ++s) {
         const int R = f.radix[s];
-        if (R == 8) fft_stage<T, 8, INV, (EMAX + 7) / 8>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
-        else if (R == 4) fft_stage<T, 4, INV, (EMAX + 3) / 4>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
-        else if (R == 3) fft_stage<T, 3, INV, (EMAX + 2) / 3>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
-        else fft_stage<T, 2, INV, (EMAX + 1) / 2>(buf, ES, f.L, logB, Ns, tw, tid, nthr);
+        if (R == 8) fft_stage<T, 8, INV, (EMAX + 7) / 8>(buf, ES, f.L, logB, Ns, logNs, tw, tid, nthr);
+        else if (R == 4) fft_stage<T, 4, INV, (EMAX + 3) / 4>(buf, ES, f.L, logB, Ns, logNs, tw, tid, nthr);
+        else if (R == 3) fft_stage<T, 3, INV, (EMAX + 2) / 3>(buf, ES, f.L, logB, Ns, logNs, tw, tid, nthr);
+        else fft_stage<T, 2, INV, (EMAX + 1) / 2>(buf, ES, f.L, logB, Ns, logNs, tw, tid, nthr);
         Ns *= R;
+        // Ns stays a power of two until the first radix-3 stage (radix 3 comes last)
+        logNs = (R == 3 || logNs < 0) ? -1 : logNs + (R == 8 ? 3 : R == 4 ? 2 : 1);
     }
 }
 
@@ -248,24 +252,41 @@ __device__ __forceinline__ cx<T> kmul(cx<T> k, cx<T> a) {
     else return cmul(k, a);
 }
 
-template <typename T, int S, bool RC, bool GUARD>
-__device__ __forceinline__ void cn_segment_solve(cx<T> (&v)[S], int cnt, cx<T> left, cx<T> right,
-                                                 cx<T> kappa, const cx<T>* ta, const cx<T>* tp,
-                                                 const cx<T>* tq, const cx<T>* pend,
-                                                 const cx<T>* qbeg, int e0, int seg, int nseg,
-                                                 cx<T>* dl, cx<T>* xf, int line, int nlines) {
+// Arithmetic type of the tridiagonal recurrences: the storage type in
+// imaginary time (real coefficients; renormalised every step), FP64 in real
+// time.  Rounding the Thomas factors to FP32 would make every step
+// non-unitary by O(1e-7) with the same sign each step, a systematic norm drift
+// over long runs; FP64 factors and recurrences leave only the unbiased rounding
+// of the FP32 state.
+template <typename T, bool RC>
+using cn_acc_t = typename std::conditional<RC, T, double>::type;
+
+template <typename A, typename T>
+__device__ __forceinline__ cx<A> widen(cx<T> v) { return cx<A>{A(v.x), A(v.y)}; }
+
+template <typename T, int S, bool RC, bool GUARD, typename TT>
+__device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], int cnt,
+                                                 cx<cn_acc_t<T, RC>> left,
+                                                 cx<cn_acc_t<T, RC>> right,
+                                                 cx<cn_acc_t<T, RC>> kappa, const cx<TT>* ta,
+                                                 const cx<TT>* tp, const cx<TT>* tq,
+                                                 const cx<cn_acc_t<T, RC>>* pend,
+                                                 const cx<cn_acc_t<T, RC>>* qbeg, int e0, int seg,
+                                                 int nseg, cx<cn_acc_t<T, RC>>* dl,
+                                                 cx<cn_acc_t<T, RC>>* xf, int line, int nlines) {
+    using A = cn_acc_t<T, RC>;
     const bool act = cnt > 0;
-    cx<T> al[S];
+    cx<A> al[S];
 #pragma unroll
     for (int i = 0; i < S; ++i)
-        if (act && (!GUARD || i < cnt)) al[i] = ta[e0 + i];
+        if (act && (!GUARD || i < cnt)) al[i] = widen<A>(ta[e0 + i]);
     // 1. r'_i = u_{i-1} + u_{i+1} + kappa u_i
-    cx<T> prev = left;
+    cx<A> prev = left;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
-            const cx<T> cur = v[i];
-            cx<T> nxt = right;
+            const cx<A> cur = v[i];
+            cx<A> nxt = right;
             if (i + 1 < S) {
                 if (!GUARD || i + 1 < cnt) nxt = v[(i + 1 < S) ? i + 1 : i];
             }
@@ -274,7 +295,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<T> (&v)[S], int cnt, cx<T> l
         }
     }
     // 2. forward recurrence, zero carry
-    cx<T> dcur = {T(0), T(0)};
+    cx<A> dcur = {A(0), A(0)};
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
@@ -286,13 +307,13 @@ __device__ __forceinline__ void cn_segment_solve(cx<T> (&v)[S], int cnt, cx<T> l
     __syncthreads();
     if (act) {
         // 3. true d_{e0-1} from the segments on the left
-        cx<T> c = {T(0), T(0)};
+        cx<A> c = {A(0), A(0)};
         for (int k = 0; k < seg; ++k) c = dl[k * nlines + line] + kmul<RC>(pend[k], c);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(tp[e0 + i], c);
+            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(widen<A>(tp[e0 + i]), c);
         // 4. back substitution, zero carry
-        cx<T> xcur = {T(0), T(0)};
+        cx<A> xcur = {A(0), A(0)};
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
             if (!GUARD || i < cnt) {
@@ -304,11 +325,11 @@ __device__ __forceinline__ void cn_segment_solve(cx<T> (&v)[S], int cnt, cx<T> l
     }
     __syncthreads();
     if (act) {
-        cx<T> c = {T(0), T(0)};
+        cx<A> c = {A(0), A(0)};
         for (int k = nseg - 1; k > seg; --k) c = xf[k * nlines + line] + kmul<RC>(qbeg[k], c);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(tq[e0 + i], c);
+            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(widen<A>(tq[e0 + i]), c);
     }
 }
 

@@ -15,48 +15,52 @@ namespace {
 
 constexpr int kMaxThreads = 1024;
 
-template <typename T>
+// Tables are complex FP64 in the workspace (see dgpe_internal.h).
 struct CnTab {
-    const cx<T>* a;
-    const cx<T>* p;
-    const cx<T>* q;
-    const cx<T>* pend;
-    const cx<T>* qbeg;
+    const cx<double>* a;
+    const cx<double>* p;
+    const cx<double>* q;
+    const cx<double>* pend;
+    const cx<double>* qbeg;
 };
 
-template <typename T>
-CnTab<T> tab_of(const void* base, int N) {
-    const cx<T>* t = (const cx<T>*)base;
-    return CnTab<T>{t + TAB_ALPHA * N, t + TAB_P * N, t + TAB_Q * N, t + TAB_PEND * N,
-                    t + TAB_QBEG * N};
+CnTab tab_of(const void* base, int N) {
+    const cx<double>* t = (const cx<double>*)base;
+    return CnTab{t + TAB_ALPHA * N, t + TAB_P * N, t + TAB_Q * N, t + TAB_PEND * N,
+                 t + TAB_QBEG * N};
 }
 
-// LDS: A1[nseg*ZB] | A2[nseg*ZB] | alpha[L] | P[L] | Q[L] | pend[nseg] | qbeg[nseg]
+template <typename A>
+__device__ __forceinline__ cx<A> narrow_tab(cx<double> v) { return cx<A>{A(v.x), A(v.y)}; }
+
+// LDS: A1[nseg*ZB] | A2[nseg*ZB] (arithmetic type) | alpha[L] | P[L] | Q[L] | pend | qbeg
 template <typename T, int S, bool RC, bool GUARD>
-__global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads)
-    k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab<T> tg,
-                 cx<T> kappa, double* __restrict__ norm_partials) {
+__global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2 : kMaxThreads)
+    k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab tg,
+                 cx<double> kappa64, double* __restrict__ norm_partials) {
+    using A = cn_acc_t<T, RC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_red[kMaxThreads / 64];
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ZB = 1 << logZB;
     const int nsl = nseg << logZB;
-    cx<T>* A1 = reinterpret_cast<cx<T>*>(smem_raw);
-    cx<T>* A2 = A1 + nsl;
-    cx<T>* ta = A2 + nsl;
-    cx<T>* tp = ta + L;
-    cx<T>* tq = tp + L;
-    cx<T>* pe = tq + L;
-    cx<T>* qb = pe + nseg;
+    cx<A>* A1 = reinterpret_cast<cx<A>*>(smem_raw);
+    cx<A>* A2 = A1 + nsl;
+    cx<A>* ta = A2 + nsl;
+    cx<A>* tp = ta + L;
+    cx<A>* tq = tp + L;
+    cx<A>* pe = tq + L;
+    cx<A>* qb = pe + nseg;
     for (int i = tid; i < L; i += nthr) {
-        ta[i] = tg.a[i];
-        tp[i] = tg.p[i];
-        tq[i] = tg.q[i];
+        ta[i] = narrow_tab<A>(tg.a[i]);
+        tp[i] = narrow_tab<A>(tg.p[i]);
+        tq[i] = narrow_tab<A>(tg.q[i]);
     }
     for (int i = tid; i < nseg; i += nthr) {
-        pe[i] = tg.pend[i];
-        qb[i] = tg.qbeg[i];
+        pe[i] = narrow_tab<A>(tg.pend[i]);
+        qb[i] = narrow_tab<A>(tg.qbeg[i]);
     }
+    const cx<A> kappa = narrow_tab<A>(kappa64);
     const int ncb = C >> logZB;
     const int o = blockIdx.x / ncb;
     const int c0 = (blockIdx.x - o * ncb) << logZB;
@@ -65,11 +69,11 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads
     const int e0 = seg * S;
     const int cnt = (seg < nseg) ? min(S, L - e0) : 0;
     cx<T>* base = f + (size_t)o * L * C + c0 + cl;
-    cx<T> v[S];
+    cx<A> v[S];
 #pragma unroll
     for (int i = 0; i < S; ++i)
-        if (!GUARD || i < cnt) v[i] = base[(size_t)(e0 + i) * C];
-    cx<T> lastv = v[S - 1];
+        if (!GUARD || i < cnt) v[i] = widen<A>(base[(size_t)(e0 + i) * C]);
+    cx<A> lastv = v[S - 1];
     if (GUARD) {
 #pragma unroll
         for (int i = 0; i < S; ++i)
@@ -80,20 +84,21 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads
         A2[seg * ZB + cl] = lastv;
     }
     __syncthreads();
-    cx<T> left = {T(0), T(0)}, right = {T(0), T(0)};
+    cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
     if (cnt > 0) {
         if (seg > 0) left = A2[(seg - 1) * ZB + cl];
         if (seg + 1 < nseg) right = A1[(seg + 1) * ZB + cl];
     }
     __syncthreads();  // neighbour reads done: A2 becomes the forward carries, A1 the backward ones
-    cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta + 0, tp, tq, pe, qb, e0, seg,
+    cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta, tp, tq, pe, qb, e0, seg,
                                       nseg, A2, A1, cl, ZB);
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
-            base[(size_t)(e0 + i) * C] = v[i];
-            acc += double(abs2(v[i]));
+            const cx<T> o = {T(v[i].x), T(v[i].y)};
+            base[(size_t)(e0 + i) * C] = o;
+            acc += double(abs2(o));
         }
     }
     if (norm_partials) {
@@ -103,16 +108,25 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads
 }
 
 // Standalone z sweep of B = 2^logB contiguous lines, staged through LDS.
+// LDS: P (Nz rows, storage type) | carries (arithmetic type) | pend | qbeg
 template <typename T, int SZ, bool RC, bool GUARD>
 __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int logB, int ES,
-                                             CnTab<T> tg, cx<T> kappa) {
+                                             CnTab tg, cx<double> kappa64) {
+    using A = cn_acc_t<T, RC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<T>* P = reinterpret_cast<cx<T>*>(smem_raw);
     const int B = 1 << logB;
     const int nseg = (Nz + SZ - 1) / SZ;
-    cx<T>* dl = P + Nz * ES;
-    cx<T>* xf = dl + nseg * B;
+    cx<A>* dl = reinterpret_cast<cx<A>*>(smem_raw + (((size_t)Nz * ES * sizeof(cx<T>) + 15) & ~size_t(15)));
+    cx<A>* xf = dl + nseg * B;
+    cx<A>* pe = xf + nseg * B;
+    cx<A>* qb = pe + nseg;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int i = tid; i < nseg; i += nthr) {
+        pe[i] = narrow_tab<A>(tg.pend[i]);
+        qb[i] = narrow_tab<A>(tg.qbeg[i]);
+    }
+    const cx<A> kappa = narrow_tab<A>(kappa64);
     cx<T>* base = f + (size_t)blockIdx.x * B * Nz;
     const int total = B * Nz;
     for (int g = tid; g < total; g += nthr) {
@@ -124,21 +138,21 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
     const int seg = tid >> logB;
     const int e0 = seg * SZ;
     const int cnt = (seg < nseg) ? min(SZ, Nz - e0) : 0;
-    cx<T> v[SZ];
-    cx<T> left = {T(0), T(0)}, right = {T(0), T(0)};
+    cx<A> v[SZ];
+    cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) v[i] = P[(e0 + i) * ES + bl];
-        if (e0 > 0) left = P[(e0 - 1) * ES + bl];
-        if (e0 + cnt < Nz) right = P[(e0 + cnt) * ES + bl];
+            if (!GUARD || i < cnt) v[i] = widen<A>(P[(e0 + i) * ES + bl]);
+        if (e0 > 0) left = widen<A>(P[(e0 - 1) * ES + bl]);
+        if (e0 + cnt < Nz) right = widen<A>(P[(e0 + cnt) * ES + bl]);
     }
-    cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, tg.a, tg.p, tg.q, tg.pend,
-                                       tg.qbeg, e0, seg, nseg, dl, xf, bl, B);
+    cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, tg.a, tg.p, tg.q, pe, qb, e0,
+                                          seg, nseg, dl, xf, bl, B);
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = v[i];
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = cx<T>{T(v[i].x), T(v[i].y)};
     }
     __syncthreads();
     for (int g = tid; g < total; g += nthr) {
@@ -171,11 +185,12 @@ hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
     const int logZB = p.lc.logZB[axis];
     const int nseg = (L + S - 1) / S;
     const int threads = nseg << logZB;
-    const CnTab<T> tg = tab_of<T>(p.cntab[axis][conjugate ? 1 : 0], L);
+    const CnTab tg = tab_of(p.cntab[axis][conjugate ? 1 : 0], L);
     const cx_coef k = cn_kappa(p, axis, conjugate);
-    const cx<T> kappa = {T(k.re), T(k.im)};
+    const cx<double> kappa = {k.re, k.im};
     const int blocks = cn_strided_blocks(p, axis);
-    const size_t sm = (size_t)(2 * threads + 3 * L + 2 * nseg) * sizeof(cx<T>);
+    const size_t asz = (p.imag ? sizeof(T) : sizeof(double)) * 2;
+    const size_t sm = (size_t)(2 * threads + 3 * L + 2 * nseg) * asz;
     const bool guard = (L % S) != 0;
 #define DGPE_CN(SV, RCV, GV)                                                                      \
     hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV>), dim3(blocks), dim3(threads), sm, p.stream, \
@@ -203,11 +218,12 @@ hipError_t launch_cn_z(const Plan& p, void* f, bool conjugate) {
     const int es = B + 1;
     const int S = p.lc.seg[2];
     const int nseg = (Nz + S - 1) / S;
-    const size_t sm = (size_t)(Nz * es + 2 * nseg * B) * sizeof(cx<T>);
+    const size_t sm = (((size_t)Nz * es * sizeof(cx<T>) + 15) & ~size_t(15)) +
+                      (size_t)(2 * nseg * B + 2 * nseg) * sizeof(cx<double>);
     const int blocks = (p.n[0] * p.n[1]) >> logB;
-    const CnTab<T> tg = tab_of<T>(p.cntab[2][conjugate ? 1 : 0], Nz);
+    const CnTab tg = tab_of(p.cntab[2][conjugate ? 1 : 0], Nz);
     const cx_coef k = cn_kappa(p, 2, conjugate);
-    const cx<T> kappa = {T(k.re), T(k.im)};
+    const cx<double> kappa = {k.re, k.im};
     const bool guard = (Nz % S) != 0;
 #define DGPE_CNZ(SV, RCV, GV)                                                                     \
     hipLaunchKernelGGL((k_cn_z<T, SV, RCV, GV>), dim3(blocks), dim3(p.lc.threads), sm, p.stream, \

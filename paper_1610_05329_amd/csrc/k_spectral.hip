@@ -21,6 +21,9 @@ namespace {
 constexpr int kEmax = 16;  // max elements per thread in an LDS FFT
 constexpr int kLU = 4;     // global loads in flight per thread in tile loads
 
+// FFT passes: occupancy hint (none: forcing 4 waves per SIMD spills)
+#define DGPE_FFT_OCC
+
 template <typename T>
 struct V2 {};
 template <>
@@ -92,7 +95,7 @@ enum { SRC_DENSITY = 0, SRC_ADJ_S = 1 };
 // P1 (and its adjoint twin): real field along z-lines -> half spectrum.
 // Block: B = 2^logB consecutive lines (x, y0..y0+B-1), M = Nz/2.
 template <typename T, int SRC>
-__global__ void __launch_bounds__(256) k_r2c_z(const cx<T>* __restrict__ psi,
+__global__ void __launch_bounds__(256) DGPE_FFT_OCC k_r2c_z(const cx<T>* __restrict__ psi,
                                               const cx<T>* __restrict__ psin,
                                               const T* __restrict__ phin, cx<T>* __restrict__ spec,
                                               int Nx, int Ny, int Nz, int logB, int ES, FftDesc fz,
@@ -190,7 +193,7 @@ __global__ void __launch_bounds__(256) k_r2c_z(const cx<T>* __restrict__ psi,
 
 // P2 / P4: FFT along contiguous rows of length L (the y axis of S).
 template <typename T, bool INV>
-__global__ void __launch_bounds__(256) k_rows(cx<T>* __restrict__ spec, int nrows, int L,
+__global__ void __launch_bounds__(256) DGPE_FFT_OCC k_rows(cx<T>* __restrict__ spec, int nrows, int L,
                                              FastDiv divL, int logB, int ES, FftDesc f,
                                              const cx<T>* __restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -231,7 +234,7 @@ __global__ void __launch_bounds__(256) k_rows(cx<T>* __restrict__ spec, int nrow
 // by U_R(k)/Nt (real, even in kx and ky: table indexed by |kx|, |ky|), inverse
 // FFT along x.
 template <typename T>
-__global__ void __launch_bounds__(256) k_xmul(cx<T>* __restrict__ spec, int Nx, int Ny, int logB,
+__global__ void __launch_bounds__(256) DGPE_FFT_OCC k_xmul(cx<T>* __restrict__ spec, int Nx, int Ny, int logB,
                                              int ES, FftDesc fx, const cx<T>* __restrict__ tw,
                                              const T* __restrict__ ukern) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -341,18 +344,22 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
                                                  int Nz, int logB, int ES, FftDesc fz,
                                                  const cx<T>* __restrict__ twz,
                                                  const cx<T>* __restrict__ twr2c,
-                                                 const cx<T>* __restrict__ cntab, cx<T> kappa,
+                                                 const cx<double>* __restrict__ cntab,
+                                                 cx<double> kappa64,
                                                  const double* __restrict__ sigma, TrapGeo geo,
-                                                 Phys ph) {
+                                                 Phys ph, int fcap) {
+    using A = cn_acc_t<T, RC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int M = Nz >> 1;
     const int nseg = (Nz + SZ - 1) / SZ;
+    // F: the spectrum tile, later the carries; fcap >= max((M+1) ES, carries)
     cx<T>* F = reinterpret_cast<cx<T>*>(smem_raw);
-    cx<T>* P = F + (M + 1) * ES;
+    cx<T>* P = F + fcap;
     cx<T>* stw = P + Nz * ES;
     cx<T>* sr2c = stw + M;
-    cx<T>* spe = sr2c + M + 1;
-    cx<T>* sqb = spe + nseg;
+    const size_t off = ((size_t)(fcap + Nz * ES + M + M + 1) * sizeof(cx<T>) + 15) & ~size_t(15);
+    cx<A>* spe = reinterpret_cast<cx<A>*>(smem_raw + off);
+    cx<A>* sqb = spe + nseg;
     const int B = 1 << logB;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ngy = Ny >> logB;
@@ -360,8 +367,8 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     const int y0 = (blockIdx.x - x * ngy) << logB;
     const size_t line0 = (size_t)x * Ny + y0;
     for (int i = tid; i < nseg; i += nthr) {
-        spe[i] = cntab[TAB_PEND * Nz + i];
-        sqb[i] = cntab[TAB_QBEG * Nz + i];
+        spe[i] = widen<A>(cntab[TAB_PEND * Nz + i]);
+        sqb[i] = widen<A>(cntab[TAB_QBEG * Nz + i]);
     }
     c2r_front<T>(F, stw, sr2c, spec, twz, twr2c, Nx, Ny, M, logB, ES, fz, line0);
 
@@ -405,20 +412,21 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     __syncthreads();
 
     // Crank-Nicolson along z: thread -> (line b, segment s)
-    cx<T>* dl = F;  // F is dead now; carries reuse it
-    cx<T>* xf = F + nseg * B;
+    cx<A>* dl = reinterpret_cast<cx<A>*>(F);  // F is dead now; carries reuse it
+    cx<A>* xf = dl + nseg * B;
+    const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
     const int bl = tid & (B - 1);
     const int seg = tid >> logB;
     const int e0 = seg * SZ;
     const int cnt = (seg < nseg) ? min(SZ, Nz - e0) : 0;
-    cx<T> v[SZ];
-    cx<T> left = {T(0), T(0)}, right = {T(0), T(0)};
+    cx<A> v[SZ];
+    cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) v[i] = P[(e0 + i) * ES + bl];
-        if (e0 > 0) left = P[(e0 - 1) * ES + bl];
-        if (e0 + cnt < Nz) right = P[(e0 + cnt) * ES + bl];
+            if (!GUARD || i < cnt) v[i] = widen<A>(P[(e0 + i) * ES + bl]);
+        if (e0 > 0) left = widen<A>(P[(e0 - 1) * ES + bl]);
+        if (e0 + cnt < Nz) right = widen<A>(P[(e0 + cnt) * ES + bl]);
     }
     cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, cntab + TAB_ALPHA * Nz,
                                        cntab + TAB_P * Nz, cntab + TAB_Q * Nz, spe, sqb, e0, seg,
@@ -427,7 +435,7 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = v[i];
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = cx<T>{T(v[i].x), T(v[i].y)};
     }
     __syncthreads();
     for (int g = tid; g < total; g += nthr) {
@@ -498,10 +506,19 @@ inline size_t sm_r2c(const Plan& p, int es, size_t csz) {
     const int M = p.n[2] / 2;
     return (size_t)(M * es + M + M + 1) * csz;
 }
+// capacity (in complex values of the storage type) of the spectrum tile that
+// later holds the z carries (arithmetic type, at most 16 bytes each)
+inline int c2r_fcap(const Plan& p, int es, size_t csz) {
+    const int M = p.n[2] / 2;
+    const int nseg = (p.n[2] + p.lc.seg[2] - 1) / p.lc.seg[2];
+    const size_t carries = ((size_t)2 * nseg * ((size_t)1 << p.lc.logB_z) * 16 + csz - 1) / csz;
+    return (int)std::max<size_t>((size_t)(M + 1) * es, carries);
+}
 inline size_t sm_c2r_step(const Plan& p, int es, size_t csz) {
     const int M = p.n[2] / 2;
     const int nseg = (p.n[2] + p.lc.seg[2] - 1) / p.lc.seg[2];
-    return (size_t)((M + 1) * es + p.n[2] * es + M + M + 1 + 2 * nseg) * csz;
+    const size_t off = ((size_t)(c2r_fcap(p, es, csz) + p.n[2] * es + M + M + 1) * csz + 15) & ~size_t(15);
+    return off + (size_t)2 * nseg * 16;
 }
 inline size_t sm_c2r_phi(const Plan& p, int es, size_t csz) {
     const int M = p.n[2] / 2;
@@ -574,16 +591,16 @@ hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
-    const cx<T> kappa = {T(k.re), T(k.im)};
+    const cx<double> kappa = {k.re, k.im};
     Phys ph{p.dt, p.g, p.gd, amp, p.imag ? 1 : 0};
-    const cx<T>* tab = (const cx<T>*)p.cntab[2][0];
+    const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
     const int S = p.lc.seg[2];
     const bool guard = (p.n[2] % S) != 0;
 #define DGPE_C2R_STEP(SZV, RCV, GV)                                                                \
     hipLaunchKernelGGL((k_c2r_step<T, SZV, RCV, GV>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm, \
                        p.stream, (cx<T>*)psi, (const cx<T>*)p.spec, p.n[0], p.n[1], p.n[2],         \
                        p.lc.logB_z, es, p.fz, (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, tab,    \
-                       kappa, sigma, make_geo(p), ph)
+                       kappa, sigma, make_geo(p), ph, c2r_fcap(p, es, sizeof(cx<T>)))
 #define DGPE_C2R_S(SZV)                              \
     if (p.imag) {                                    \
         if (guard) DGPE_C2R_STEP(SZV, true, true);   \
