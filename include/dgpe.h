@@ -80,6 +80,7 @@ typedef enum {
 #define DGPE_PARAM_TRAP_GAMMA 4
 #define DGPE_PARAM_DT 5
 #define DGPE_PARAM_REAL_TIME 6 /* value 1: real time, 0: imaginary time */
+#define DGPE_PARAM_FAST_FFT 7  /* 1 (default): compiled two-factor FFT passes where available; 0: generic passes only */
 
 /* adjoint objectives */
 #define DGPE_OBJ_ENERGY 0
@@ -118,8 +119,8 @@ dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[
                              uint32_t mode, void* workspace, size_t workspace_bytes,
                              void* hip_stream);
 
-/* Change one physical parameter (DGPE_PARAM_*).  DT and REAL_TIME rebuild the
- * Thomas tables (synchronous); the others take effect at the next launch. */
+/* Change one parameter (DGPE_PARAM_*).  DT and REAL_TIME rebuild the Thomas
+ * tables (synchronous); the others take effect at the next launch. */
 dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value);
 
 /* Redirect subsequent work to another HIP stream. */

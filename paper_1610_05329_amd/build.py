@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgpe.so")
-SOURCES = ["dgpe_api.hip", "k_spectral.hip", "k_cn.hip", "k_misc.hip"]
+SOURCES = ["dgpe_api.hip", "k_spectral.hip", "k_cn.hip", "k_misc.hip", "k_fft2.hip"]
 ARCH = os.environ.get("DGPE_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

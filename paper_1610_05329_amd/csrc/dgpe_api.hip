@@ -607,6 +607,7 @@ dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[
     p->fx = factor(n[0]);
     p->fy = factor(n[1]);
     p->fz = factor(n[2] / 2);
+    p->fast = true;
     st = f32 ? build_tables<float>(*p) : build_tables<double>(*p);
     if (st != DGPE_OK) {
         delete p;
@@ -626,6 +627,10 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
         case DGPE_PARAM_TRAP_NU: p.trap[0] = value; return DGPE_OK;
         case DGPE_PARAM_TRAP_LAMBDA: p.trap[1] = value; return DGPE_OK;
         case DGPE_PARAM_TRAP_GAMMA: p.trap[2] = value; return DGPE_OK;
+        case DGPE_PARAM_FAST_FFT:
+            if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "FAST_FFT takes 0 or 1");
+            p.fast = value == 1.0;
+            return DGPE_OK;
         case DGPE_PARAM_DT:
             if (!(value > 0)) return fail(DGPE_EINVAL, "dt must be > 0");
             p.dt = value;

@@ -62,6 +62,7 @@ struct Plan {
     size_t red_count;
     FftDesc fx, fy, fz;
     Launch lc;
+    bool fast;  // use the two-factor register FFT passes where compiled
 };
 
 size_t workspace_layout(const int n[3], bool f32, size_t* offs /* [16] or null */);
@@ -114,6 +115,19 @@ hipError_t launch_reduce(const Plan& p, const double* partials, int nblocks, int
 hipError_t launch_norm_finalize(const Plan& p, const double* partials, int nblocks, double* sigma);
 
 int cn_strided_blocks(const Plan& p, int axis);
+
+// Two-factor register FFT passes (k_fft2.hip); false when the length has no
+// compiled fast path (the caller then uses the generic Stockham kernel).
+template <typename T>
+bool fast_rows(const Plan& p, bool inverse);
+template <typename T>
+bool fast_xmul(const Plan& p);
+template <typename T>
+bool fast_r2c(const Plan& p, const void* psi, const double* sigma);
+template <typename T>
+bool fast_c2r_phi(const Plan& p, void* phi);
+template <typename T>
+bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp);
 
 // kappa = 1/A - 2 of the scaled Crank-Nicolson right-hand side (conj(A) for the adjoint)
 struct cx_coef {

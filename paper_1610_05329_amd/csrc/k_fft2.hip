@@ -1,0 +1,604 @@
+// Fast spectral passes: the two-factor register FFT (fft_reg.h) for the
+// lengths L = R1 R2 listed in fast_split().  Each pass reads and writes HBM
+// once with coalesced accesses and exchanges data through LDS once per
+// transform (the generic Stockham kernels in k_spectral.hip cover every
+// other length).  Same results as the generic passes up to rounding order.
+#include "fft_reg.h"
+
+namespace dgpe {
+
+namespace {
+
+// elements of one block's tile: 4096 complex in FP32, 2048 in FP64
+template <typename T>
+constexpr int tile_budget() { return sizeof(T) == 4 ? 4096 : 2048; }
+
+template <typename T, int R1, int L>
+constexpr int rows_per_block() {
+    int nb = 32;
+    while (nb > 1 && (nb * L > tile_budget<T>() || nb * R1 > 256)) nb >>= 1;
+    return nb;
+}
+
+// ---------------------------------------------------------------------------
+// P2 / P4: FFT along contiguous rows of length L = R1 R2 (the y axis of S).
+// Lanes: t fastest (t < R1 threads per row), NB rows per block.
+// ---------------------------------------------------------------------------
+template <typename T, int R1, int R2, bool INV>
+__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+    k_rows2(cx<T>* __restrict__ spec, int nrows, const cx<T>* __restrict__ tw) {
+    constexpr int L = R1 * R2;
+    constexpr int NB = rows_per_block<T, R1, L>();
+    constexpr int SB = R2 * (R1 + 1);
+    __shared__ cx<T> xb[NB * SB];
+    __shared__ cx<T> stw[L];
+    const int tid = threadIdx.x;
+    const int t = tid % R1, b = tid / R1;
+    for (int i = tid; i < L; i += NB * R1) stw[i] = tw[i];
+    const int row = blockIdx.x * NB + b;
+    const bool ok = row < nrows;
+    cx<T>* base = spec + (size_t)row * L;
+    cx<T> v[R2];
+    if (ok) {
+#pragma unroll
+        for (int n = 0; n < R2; ++n) v[n] = base[t + R1 * n];
+    }
+    __syncthreads();
+    if (ok) {
+        rdft<T, R2, INV>(v);
+        twiddle_phase<T, R2, INV>(v, t, stw);
+#pragma unroll
+        for (int k = 0; k < R2; ++k) xb[b * SB + k * (R1 + 1) + t] = v[k];
+    }
+    __syncthreads();
+    if (ok && t < R2) {
+        cx<T> w[R1];
+#pragma unroll
+        for (int n = 0; n < R1; ++n) w[n] = xb[b * SB + t * (R1 + 1) + n];
+        rdft<T, R1, INV>(w);
+#pragma unroll
+        for (int k = 0; k < R1; ++k) base[t + R2 * k] = w[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P3: FFT along x (stride Ny) of NB adjacent columns at one kz, multiply by
+// U_R/Nt (quarter table indexed by |kx|, |ky|), inverse FFT along x.
+// Lanes: b fastest (NB columns), t < R1 threads per column.
+// ---------------------------------------------------------------------------
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+    k_xmul2(cx<T>* __restrict__ spec, int Ny, const cx<T>* __restrict__ tw,
+            const T* __restrict__ ukern) {
+    constexpr int L = R1 * R2;  // Nx
+    constexpr int NB = rows_per_block<T, R1, L>();
+    __shared__ cx<T> xb[NB * L];
+    __shared__ cx<T> stw[L];
+    const int tid = threadIdx.x;
+    const int b = tid % NB, t = tid / NB;
+    for (int i = tid; i < L; i += NB * R1) stw[i] = tw[i];
+    const int ngy = Ny / NB;
+    const int kz = blockIdx.x / ngy;
+    const int y0 = (blockIdx.x - kz * ngy) * NB;
+    cx<T>* base = spec + (size_t)kz * L * Ny + y0 + b;
+    cx<T> v[R2];
+#pragma unroll
+    for (int n = 0; n < R2; ++n) v[n] = base[(size_t)(t + R1 * n) * Ny];
+    __syncthreads();
+    rdft<T, R2, false>(v);
+    twiddle_phase<T, R2, false>(v, t, stw);
+#pragma unroll
+    for (int k = 0; k < R2; ++k) xb[(k * R1 + t) * NB + b] = v[k];
+    __syncthreads();
+    cx<T> w[R1];
+    if (t < R2) {
+#pragma unroll
+        for (int n = 0; n < R1; ++n) w[n] = xb[(t * R1 + n) * NB + b];
+        rdft<T, R1, false>(w);
+        // w[k1] = X[kx = t + R2 k1]
+        const int hx = L / 2 + 1, hy = Ny / 2 + 1;
+        const int ky0 = y0 + b;
+        const int ky = min(ky0, Ny - ky0);
+        const T* urow = ukern + (size_t)kz * hx * hy + ky;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) {
+            const int kx0 = t + R2 * k;
+            const int kx = min(kx0, L - kx0);
+            w[k] = urow[(size_t)kx * hy] * w[k];
+        }
+        // inverse: the layout of w is the phase-A layout of the (R2, R1) split
+        rdft<T, R1, true>(w);
+        twiddle_phase<T, R1, true>(w, t, stw);
+    }
+    __syncthreads();
+    if (t < R2) {
+#pragma unroll
+        for (int j = 0; j < R1; ++j) xb[(j * R2 + t) * NB + b] = w[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < R2; ++u) v[u] = xb[(t * R2 + u) * NB + b];
+    rdft<T, R2, true>(v);
+#pragma unroll
+    for (int l = 0; l < R2; ++l) base[(size_t)(t + R1 * l) * Ny] = v[l];
+}
+
+// packed real-to-complex post-processing (see k_spectral.hip)
+template <typename T>
+__device__ __forceinline__ cx<T> r2c_post2(cx<T> zk, cx<T> zm, cx<T> w) {
+    const T h = T(0.5);
+    const cx<T> E = {h * (zk.x + zm.x), h * (zk.y - zm.y)};
+    const cx<T> O = {h * (zk.y + zm.y), -h * (zk.x - zm.x)};
+    return E + cmul(w, O);
+}
+
+// ---------------------------------------------------------------------------
+// P1: density |psi|^2 sigma of NB z-lines packed as z_j = n_{2j} + i n_{2j+1},
+// FFT of length M = Nz/2 = R1 R2, post-processing into the half spectrum,
+// kz-major store.  Lanes: t fastest.
+// ---------------------------------------------------------------------------
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+    k_r2c2(const cx<T>* __restrict__ psi, cx<T>* __restrict__ spec, int Nx, int Ny,
+           const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
+           const double* __restrict__ sigma) {
+    constexpr int M = R1 * R2;
+    constexpr int NB = rows_per_block<T, R1, M>();
+    constexpr int NT = NB * R1;
+    constexpr int SB = R2 * (R1 + 1);  // >= M + 1
+    __shared__ cx<T> xb[NB * SB];
+    __shared__ cx<T> stw[M];
+    __shared__ cx<T> sr2c[M + 1];
+    const int tid = threadIdx.x;
+    const int t = tid % R1, b = tid / R1;
+    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
+    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
+    const int ngy = Ny / NB;
+    const int x = blockIdx.x / ngy;
+    const int y0 = (blockIdx.x - x * ngy) * NB;
+    const size_t line0 = (size_t)x * Ny + y0;
+    const T sig = sigma ? T(sigma[0]) : T(1);
+    const cx<T>* base = psi + (line0 + b) * (2 * M);
+    cx<T> v[R2];
+#pragma unroll
+    for (int n = 0; n < R2; ++n) {
+        const int j = t + R1 * n;
+        const cx<T> a = base[2 * j], c = base[2 * j + 1];
+        v[n] = cx<T>{abs2(a) * sig, abs2(c) * sig};
+    }
+    __syncthreads();
+    rdft<T, R2, false>(v);
+    twiddle_phase<T, R2, false>(v, t, stw);
+#pragma unroll
+    for (int k = 0; k < R2; ++k) xb[b * SB + k * (R1 + 1) + t] = v[k];
+    __syncthreads();
+    cx<T> w[R1];
+    if (t < R2) {
+#pragma unroll
+        for (int n = 0; n < R1; ++n) w[n] = xb[b * SB + t * (R1 + 1) + n];
+        rdft<T, R1, false>(w);
+    }
+    __syncthreads();
+    if (t < R2) {
+#pragma unroll
+        for (int k = 0; k < R1; ++k) xb[b * SB + t + R2 * k] = w[k];  // Z in natural order
+    }
+    __syncthreads();
+    const size_t plane = (size_t)Nx * Ny;
+    for (int g = tid; g < (M + 1) * NB; g += NT) {
+        const int k = g / NB, bl = g - k * NB;
+        const cx<T> zk = xb[bl * SB + (k == M ? 0 : k)];
+        const cx<T> zm = xb[bl * SB + (k == 0 ? 0 : M - k)];
+        spec[(size_t)k * plane + line0 + bl] = r2c_post2(zk, zm, sr2c[k]);
+    }
+}
+
+// Front half of the z inverse transform for NB lines: load X_k (k <= M),
+// form Z_j, two-factor inverse FFT.  On return thread (b, t < R2) holds
+// z_m = (Phi_{2m}, Phi_{2m+1}) for m = t + R2 k in w[k] (already / Nt).
+// xin needs NB * (M + 2) entries, xb NB * R2 * (R1 + 1); they may alias.
+template <typename T, int R1, int R2, int NB>
+__device__ __forceinline__ void c2r_front2(cx<T> (&w)[R1], cx<T>* xin, cx<T>* xb, const cx<T>* stw,
+                                           const cx<T>* sr2c, const cx<T>* __restrict__ spec,
+                                           size_t plane, size_t line0, int tid, int nthr) {
+    constexpr int M = R1 * R2;
+    constexpr int SB = R2 * (R1 + 1);
+    constexpr int SI = M + 2;
+    for (int g = tid; g < (M + 1) * NB; g += nthr) {
+        const int k = g / NB, bl = g - k * NB;
+        xin[bl * SI + k] = spec[(size_t)k * plane + line0 + bl];
+    }
+    __syncthreads();
+    const int t = tid % R1, b = tid / R1;
+    const bool act = tid < NB * R1;
+    cx<T> v[R2];
+    if (act) {
+#pragma unroll
+        for (int n = 0; n < R2; ++n) {
+            const int j = t + R1 * n;
+            if (j == 0) {
+                const T x0 = xin[b * SI].x, xm = xin[b * SI + M].x;
+                v[n] = cx<T>{x0 + xm, x0 - xm};
+            } else {
+                const cx<T> xa = xin[b * SI + j], xc = xin[b * SI + M - j];
+                const cx<T> s1 = xa + conj(xc);
+                const cx<T> d1 = cmulc(xa - conj(xc), sr2c[j]);
+                v[n] = cx<T>{s1.x - d1.y, s1.y + d1.x};
+            }
+        }
+        rdft<T, R2, true>(v);
+        twiddle_phase<T, R2, true>(v, t, stw);
+    }
+    __syncthreads();  // xin reads complete before xb (which may alias) is written
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < R2; ++k) xb[b * SB + k * (R1 + 1) + t] = v[k];
+    }
+    __syncthreads();
+    if (act && t < R2) {
+#pragma unroll
+        for (int n = 0; n < R1; ++n) w[n] = xb[b * SB + t * (R1 + 1) + n];
+        rdft<T, R1, true>(w);
+    }
+}
+
+template <int R1, int R2, int NB>
+constexpr int c2r_region() {  // complex entries of the xin / xb region
+    constexpr int M = R1 * R2;
+    return NB * (M + 2) > NB * R2 * (R1 + 1) ? NB * (M + 2) : NB * R2 * (R1 + 1);
+}
+
+// Phi to a real [Nx][Ny][Nz] buffer.
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+    k_c2r_phi2(T* __restrict__ phi, const cx<T>* __restrict__ spec, int Nx, int Ny,
+               const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c) {
+    constexpr int M = R1 * R2;
+    constexpr int NB = rows_per_block<T, R1, M>();
+    constexpr int NT = NB * R1;
+    __shared__ cx<T> reg[c2r_region<R1, R2, NB>()];
+    __shared__ cx<T> stw[M];
+    __shared__ cx<T> sr2c[M + 1];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
+    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
+    const int ngy = Ny / NB;
+    const int x = blockIdx.x / ngy;
+    const int y0 = (blockIdx.x - x * ngy) * NB;
+    const size_t line0 = (size_t)x * Ny + y0;
+    cx<T> w[R1];
+    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, spec, (size_t)Nx * Ny, line0, tid, NT);
+    const int t = tid % R1, b = tid / R1;
+    if (t < R2) {
+        cx<T>* out = reinterpret_cast<cx<T>*>(phi + (line0 + b) * (2 * M));
+#pragma unroll
+        for (int k = 0; k < R1; ++k) out[t + R2 * k] = w[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P5: z inverse transform -> Phi, nonlinear phase, Crank-Nicolson along z.
+// LDS: region (xin / xb, then Phi pairs, then the z carries) | Psi tile |
+// twiddles | segment carry products.
+// ---------------------------------------------------------------------------
+struct Phys2 {
+    double dt, g, gd, amp;
+    int imag;
+    int hx, hy, hz;
+    double dx, dy, dz, cx, cy, cz;
+};
+
+template <typename T>
+__device__ __forceinline__ T trap_v0_2(const Phys2& g, int ix, int iy, int iz) {
+    const T x = T(ix - g.hx) * T(g.dx);
+    const T y = T(iy - g.hy) * T(g.dy);
+    const T z = T(iz - g.hz) * T(g.dz);
+    return T(g.cx) * x * x + T(g.cy) * y * y + T(g.cz) * z * z;
+}
+
+// lines per block of the fused z pass: the state tile (Nz (NB+1) complex) must
+// fit next to the spectral region in 64 KB of LDS
+template <typename T, int R1, int M>
+constexpr int step_nb() {
+    int nb = rows_per_block<T, R1, M>();
+    while (nb > 1 && (size_t)(2 * M) * (nb + 1) * 2 * sizeof(T) > 40 * 1024) nb >>= 1;
+    return nb;
+}
+
+template <typename T, int R1, int R2, int SZ, bool RC, bool GUARD>
+constexpr int step2_region() {
+    constexpr int M = R1 * R2;
+    constexpr int NB = step_nb<T, R1, M>();
+    constexpr int nseg = (2 * M + SZ - 1) / SZ;
+    constexpr int carries = (2 * nseg * NB * (int)sizeof(cx<cn_acc_t<T, RC>>) + (int)sizeof(cx<T>) - 1) /
+                            (int)sizeof(cx<T>);
+    constexpr int phi = NB * (M + 1);
+    constexpr int a = c2r_region<R1, R2, NB>();
+    return a > carries ? (a > phi ? a : phi) : (carries > phi ? carries : phi);
+}
+
+template <typename T, int R1, int R2, int SZ, bool RC, bool GUARD>
+constexpr int step2_threads() {
+    constexpr int M = R1 * R2;
+    constexpr int NB = step_nb<T, R1, M>();
+    constexpr int nseg = (2 * M + SZ - 1) / SZ;
+    constexpr int a = NB * R1, c = NB * nseg;
+    constexpr int m = a > c ? a : c;
+    return (m + 63) / 64 * 64;
+}
+
+template <typename T, int R1, int R2, int SZ, bool RC, bool GUARD>
+__global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ, RC, GUARD>()))
+    k_c2r_step2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
+                const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
+                const cx<double>* __restrict__ cntab, cx<double> kappa64,
+                const double* __restrict__ sigma, Phys2 ph) {
+    using A = cn_acc_t<T, RC>;
+    constexpr int M = R1 * R2;
+    constexpr int Nz = 2 * M;
+    constexpr int NB = step_nb<T, R1, M>();
+    constexpr int ES = NB + 1;
+    constexpr int NT = step2_threads<T, R1, R2, SZ, RC, GUARD>();
+    constexpr int nseg = (Nz + SZ - 1) / SZ;
+    constexpr int REG = step2_region<T, R1, R2, SZ, RC, GUARD>();
+    __shared__ cx<T> reg[REG];
+    __shared__ cx<T> P[Nz * ES];
+    __shared__ cx<T> stw[M];
+    __shared__ cx<T> sr2c[M + 1];
+    __shared__ cx<A> spe[nseg];
+    __shared__ cx<A> sqb[nseg];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
+    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
+    for (int i = tid; i < nseg; i += NT) {
+        spe[i] = widen<A>(cntab[TAB_PEND * Nz + i]);
+        sqb[i] = widen<A>(cntab[TAB_QBEG * Nz + i]);
+    }
+    const int ngy = Ny / NB;
+    const int x = blockIdx.x / ngy;
+    const int y0 = (blockIdx.x - x * ngy) * NB;
+    const size_t line0 = (size_t)x * Ny + y0;
+    cx<T> w[R1];
+    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, spec, (size_t)Nx * Ny, line0, tid, NT);
+    __syncthreads();  // reg is rewritten with the Phi pairs
+    {
+        const int t = tid % R1, b = tid / R1;
+        if (tid < NB * R1 && t < R2) {
+#pragma unroll
+            for (int k = 0; k < R1; ++k) reg[b * (M + 1) + t + R2 * k] = w[k];
+        }
+    }
+    __syncthreads();
+    // nonlinear step (pre-step density, lazily normalised) into the Psi tile
+    const double sg = sigma ? sigma[0] : 1.0;
+    const T sig = T(sg), rs = T(sqrt(sg));
+    const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
+    cx<T>* base = psi + line0 * Nz;
+    constexpr int total = NB * Nz;
+    constexpr int LU = 4;
+    for (int g0 = tid; g0 < total; g0 += LU * NT) {
+        cx<T> a[LU];
+#pragma unroll
+        for (int u = 0; u < LU; ++u) {
+            const int g = g0 + u * NT;
+            if (g < total) a[u] = base[g];
+        }
+#pragma unroll
+        for (int u = 0; u < LU; ++u) {
+            const int g = g0 + u * NT;
+            if (g < total) {
+                const int b = g / Nz, e = g - b * Nz;
+                const cx<T> fv = reg[b * (M + 1) + (e >> 1)];
+                const T phi = (e & 1) ? fv.y : fv.x;
+                const T n = abs2(a[u]) * sig;
+                const T th = dt * (amp * trap_v0_2<T>(ph, x, y0 + b, e) + gg * n + gdd * phi);
+                cx<T> r;
+                if (ph.imag) {
+                    const T f = rs * exp_of(-th);
+                    r = f * a[u];
+                } else {
+                    T sn, cs;
+                    sin_cos(th, &sn, &cs);
+                    cs *= rs;
+                    sn *= rs;
+                    r = cx<T>{a[u].x * cs + a[u].y * sn, a[u].y * cs - a[u].x * sn};
+                }
+                P[e * ES + b] = r;
+            }
+        }
+    }
+    __syncthreads();
+    // Crank-Nicolson along z: thread -> (line bl, segment seg)
+    cx<A>* dl = reinterpret_cast<cx<A>*>(reg);
+    cx<A>* xf = dl + nseg * NB;
+    const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
+    const int bl = tid % NB;
+    const int seg = tid / NB;
+    const int e0 = seg * SZ;
+    const int cnt = (seg < nseg) ? min(SZ, Nz - e0) : 0;
+    cx<A> v[SZ];
+    cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
+    if (cnt > 0) {
+#pragma unroll
+        for (int i = 0; i < SZ; ++i)
+            if (!GUARD || i < cnt) v[i] = widen<A>(P[(e0 + i) * ES + bl]);
+        if (e0 > 0) left = widen<A>(P[(e0 - 1) * ES + bl]);
+        if (e0 + cnt < Nz) right = widen<A>(P[(e0 + cnt) * ES + bl]);
+    }
+    cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, cntab + TAB_ALPHA * Nz,
+                                       cntab + TAB_P * Nz, cntab + TAB_Q * Nz, spe, sqb, e0, seg,
+                                       nseg, dl, xf, bl, NB);
+    if (cnt > 0) {
+#pragma unroll
+        for (int i = 0; i < SZ; ++i)
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = cx<T>{T(v[i].x), T(v[i].y)};
+    }
+    __syncthreads();
+    for (int g = tid; g < total; g += NT) {
+        const int b = g / Nz, e = g - b * Nz;
+        base[g] = P[e * ES + b];
+    }
+}
+
+}  // namespace
+
+// ---- dispatch --------------------------------------------------------------
+
+#define DGPE_SPLITS(X) \
+    X(4, 4) X(8, 4) X(8, 6) X(8, 8) X(12, 8) X(16, 8) X(16, 12) X(16, 16) X(24, 16) X(32, 16)
+
+template <typename T>
+int fast_rows_per_block(int L) {
+    switch (L) {
+#define DGPE_CASE(A, B) \
+    case A * B: return rows_per_block<T, A, A * B>();
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return 0;
+    }
+}
+
+template <typename T>
+bool fast_rows(const Plan& p, bool inverse) {
+    const int L = p.n[1];
+    const Split2 s = fast_split(L);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(L);
+    const int nrows = (p.n[2] / 2 + 1) * p.n[0];
+    const int blocks = (nrows + nb - 1) / nb;
+    switch (L) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        if (inverse)                                                                                 \
+            hipLaunchKernelGGL((k_rows2<T, A, B, true>), dim3(blocks), dim3(nb * A), 0, p.stream,   \
+                               (cx<T>*)p.spec, nrows, (const cx<T>*)p.tw[1]);                        \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_rows2<T, A, B, false>), dim3(blocks), dim3(nb * A), 0, p.stream,  \
+                               (cx<T>*)p.spec, nrows, (const cx<T>*)p.tw[1]);                        \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool fast_xmul(const Plan& p) {
+    const int L = p.n[0];
+    const Split2 s = fast_split(L);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(L);
+    if (p.n[1] % nb) return false;
+    const int blocks = (p.n[2] / 2 + 1) * (p.n[1] / nb);
+    switch (L) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        hipLaunchKernelGGL((k_xmul2<T, A, B>), dim3(blocks), dim3(nb * A), 0, p.stream,             \
+                           (cx<T>*)p.spec, p.n[1], (const cx<T>*)p.tw[0], (const T*)p.ukern);        \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool fast_r2c(const Plan& p, const void* psi, const double* sigma) {
+    const int M = p.n[2] / 2;
+    const Split2 s = fast_split(M);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(M);
+    if (p.n[1] % nb) return false;
+    const int blocks = p.n[0] * (p.n[1] / nb);
+    switch (M) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        hipLaunchKernelGGL((k_r2c2<T, A, B>), dim3(blocks), dim3(nb * A), 0, p.stream,              \
+                           (const cx<T>*)psi, (cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2], \
+                           (const cx<T>*)p.twr2c, sigma);                                            \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool fast_c2r_phi(const Plan& p, void* phi) {
+    const int M = p.n[2] / 2;
+    const Split2 s = fast_split(M);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(M);
+    if (p.n[1] % nb) return false;
+    const int blocks = p.n[0] * (p.n[1] / nb);
+    switch (M) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        hipLaunchKernelGGL((k_c2r_phi2<T, A, B>), dim3(blocks), dim3(nb * A), 0, p.stream, (T*)phi, \
+                           (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],             \
+                           (const cx<T>*)p.twr2c);                                                   \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
+// fused P5 for Nz/2 in {32, 64, 128} with 16-point z segments
+#define DGPE_STEP_SPLITS(X) X(8, 4) X(8, 8) X(16, 8)
+
+template <typename T>
+bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
+    const int M = p.n[2] / 2;
+    if (p.lc.seg[2] != 16) return false;
+    int nb = 0;
+    switch (M) {
+#define DGPE_CASE(A, B) \
+    case A * B: nb = step_nb<T, A, A * B>(); break;
+        DGPE_STEP_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+    if (p.n[1] % nb) return false;
+    const cx_coef k = cn_kappa(p, 2, false);
+    const cx<double> kappa = {k.re, k.im};
+    Phys2 ph{p.dt, p.g, p.gd, amp, p.imag ? 1 : 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
+             p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
+             0.5 * p.trap[2] * p.trap[2]};
+    const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
+    const int blocks = p.n[0] * (p.n[1] / nb);
+    const bool guard = (p.n[2] % 16) != 0;
+    switch (M) {
+#define DGPE_LAUNCH(A, B, RCV, GV)                                                                  \
+    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV, GV>), dim3(blocks),                          \
+                       dim3(step2_threads<T, A, B, 16, RCV, GV>()), 0, p.stream, (cx<T>*)psi,      \
+                       (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],                \
+                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph)
+#define DGPE_CASE(A, B)                                   \
+    case A * B:                                           \
+        if (p.imag) {                                     \
+            if (guard) DGPE_LAUNCH(A, B, true, true);     \
+            else DGPE_LAUNCH(A, B, true, false);          \
+        } else {                                          \
+            if (guard) DGPE_LAUNCH(A, B, false, true);    \
+            else DGPE_LAUNCH(A, B, false, false);         \
+        }                                                 \
+        return true;
+        DGPE_STEP_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+#undef DGPE_LAUNCH
+        default: return false;
+    }
+}
+
+#define DGPE_INST(T)                                                 \
+    template bool fast_rows<T>(const Plan&, bool);                   \
+    template bool fast_xmul<T>(const Plan&);                         \
+    template bool fast_r2c<T>(const Plan&, const void*, const double*); \
+    template bool fast_c2r_phi<T>(const Plan&, void*);               \
+    template bool fast_c2r_step<T>(const Plan&, void*, const double*, double);
+DGPE_INST(float)
+DGPE_INST(double)
+#undef DGPE_INST
+
+}  // namespace dgpe

@@ -531,6 +531,7 @@ int r2c_blocks(const Plan& p) { return p.n[0] * (p.n[1] >> p.lc.logB_z); }
 
 template <typename T>
 hipError_t launch_r2c_density(const Plan& p, const void* psi, const double* sigma) {
+    if (p.fast && fast_r2c<T>(p, psi, sigma)) return hipGetLastError();
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_r2c(p, es, sizeof(cx<T>));
     Phys ph{};
@@ -558,6 +559,7 @@ hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin,
 
 template <typename T>
 hipError_t launch_rows(const Plan& p, bool inverse) {
+    if (p.fast && fast_rows<T>(p, inverse)) return hipGetLastError();
     const int L = p.n[1];
     const int es = (1 << p.lc.logB_y) + 1;
     const int nrows = (p.n[2] / 2 + 1) * p.n[0];
@@ -577,6 +579,7 @@ hipError_t launch_rows(const Plan& p, bool inverse) {
 
 template <typename T>
 hipError_t launch_xmul(const Plan& p) {
+    if (p.fast && fast_xmul<T>(p)) return hipGetLastError();
     const int es = (1 << p.lc.logB_x) + 1;
     const int blocks = (p.n[2] / 2 + 1) * (p.n[1] >> p.lc.logB_x);
     const size_t sm = (size_t)(p.n[0] * es + p.n[0]) * sizeof(cx<T>);
@@ -588,6 +591,7 @@ hipError_t launch_xmul(const Plan& p) {
 
 template <typename T>
 hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
+    if (p.fast && fast_c2r_step<T>(p, psi, sigma, amp)) return hipGetLastError();
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
@@ -619,6 +623,7 @@ hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double
 
 template <typename T>
 hipError_t launch_c2r_phi(const Plan& p, void* phi_out) {
+    if (p.fast && fast_c2r_phi<T>(p, phi_out)) return hipGetLastError();
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_phi(p, es, sizeof(cx<T>));
     hipLaunchKernelGGL((k_c2r_phi<T>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm, p.stream,

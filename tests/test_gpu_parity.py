@@ -180,3 +180,31 @@ def test_bad_state_is_rejected(dg, torch_mod):
     assert b"aligned" in plan.lib.dgpe_last_error()
     with pytest.raises(ValueError):
         plan.step(torch_mod.zeros((16, 16, 8), dtype=torch_mod.complex128, device="cuda"))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("real_time", [False, True], ids=["imag", "real"])
+@pytest.mark.parametrize("shape", [((64, 128, 64), (0.3, 0.2, 0.3)), ((96, 32, 32), (0.25, 0.5, 0.5)),
+                                   ((32, 64, 128), (0.4, 0.3, 0.15))], ids=lambda s: "x".join(map(str, s[0])))
+def test_fast_and_generic_fft_paths_agree(dg, torch_mod, shape, real_time, prec):
+    """The compiled two-factor passes and the generic Stockham passes give the
+    same steps up to rounding, and both match the oracle."""
+    n, d = shape
+    cfg = W.Config("t", n, d, 0.003, (1.0, 1.2, 0.9), 30.0, 12.0, not real_time, 4, noise=1e-3, seed=8)
+    psi0 = W.noisy_gaussian(cfg)
+    outs = []
+    for fast in (1, 0):
+        plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=real_time, dtype=_dtype(torch_mod, prec))
+        plan.set("fast_fft", fast)
+        psi = plan.new_state(psi0)
+        plan.step(psi, cfg.steps)
+        outs.append(psi.cpu().numpy().astype(np.complex128))
+        phi = plan.potential(plan.new_state(psi0)).cpu().numpy()
+        outs.append(phi.astype(np.float64))
+    ref = O.evolve(O.Params.from_config(cfg), psi0, cfg.steps)
+    ref_phi = O.dipolar_potential(O.Params.from_config(cfg), np.abs(psi0) ** 2)
+    e_fast, e_gen, e_ab = _rel(outs[0], ref), _rel(outs[2], ref), _rel(outs[0], outs[2])
+    p_fast, p_gen = _rel(outs[1], ref_phi), _rel(outs[3], ref_phi)
+    _say(f"  fast {e_fast:.2e} generic {e_gen:.2e} fast-vs-generic {e_ab:.2e}; phi {p_fast:.2e} {p_gen:.2e}")
+    assert max(e_fast, e_gen, e_ab) < TOL[prec]
+    assert max(p_fast, p_gen) < (1e-13 if prec == "f64" else 2e-6)
