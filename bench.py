@@ -36,8 +36,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_256cubed.json")
 KERNEL_OF_PASS = {
-    "r2c_z": "k_r2c_z", "fft_y": "k_rows", "fft_x_mul": "k_xmul", "ifft_y": "k_rows",
-    "c2r_z_nonlinear_cn_z": "k_c2r_step", "cn_y": "k_cn_strided", "cn_x": "k_cn_strided",
+    "r2c_z": "k_r2c2", "fft_y": "k_rows2", "fft_x_mul": "k_xmul2", "ifft_y": "k_rows2",
+    "c2r_z_nonlinear_cn_z": "k_c2r_step2", "cn_y": "k_cn_strided", "cn_x": "k_cn_strided",
     "norm_reduce": "k_reduce",
 }
 
@@ -127,14 +127,24 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--summarize", metavar="DIR")
     ap.add_argument("--summary-name", default="")
+    ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
+    ap.add_argument("--command", default="")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--adjoint-steps", type=int, default=40)
+    ap.add_argument("--workload", choices=["C3", "C5"], default="C3",
+                    help="configuration of --profile-run (the JSON line always uses C3)")
     args = ap.parse_args()
 
     if args.summarize:
-        summarize(args.summarize, args.summary_name)
+        out = summarize(args.summarize, args.summary_name)
+        if args.traffic:
+            out += [""] + summarize_traffic(*args.traffic, 256 << 20, args.summary_name)
+        out.insert(1, "# command: " + args.command if args.command else "#")
+        path = os.path.join(ROOT, "profiles", f"{args.summary_name}.txt")
+        open(path, "w").write("\n".join(out) + "\n")
+        print("\n".join(out))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU slab decomposition "
@@ -156,10 +166,11 @@ def main():
         log(f"copy calibration: 5 copies of {n * 4} bytes")
         return
 
-    cfg = W.CONFIGS["C3"]
-    log(f"[bench] workload {cfg.n} imaginary time; preparing seeded state")
+    cfg = W.CONFIGS[args.workload if args.profile_run else "C3"]
+    log(f"[bench] workload {cfg.n} {'imaginary' if cfg.imag else 'real'} time; preparing seeded state")
     psi0 = W.noisy_gaussian(cfg)
-    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=torch.complex64)
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=not cfg.imag,
+                   dtype=torch.complex64)
     psi_init = plan.new_state(psi0)
     psi = psi_init.clone()
     if args.profile_run:
@@ -226,6 +237,19 @@ def main():
         log(f"[bench] adjoint FP32: {wa * 1e3 / na:.3f} ms per forward step")
         del plan_a, psia, out
         torch.cuda.empty_cache()
+        # 512 x 512 x 256 FP32 real time (the large anisotropic workload)
+        c5 = W.CONFIGS["C5"]
+        plan5 = dg.Plan(c5.n, c5.d, c5.dt, c5.trap, c5.g, c5.gd, real_time=True, dtype=torch.complex64)
+        init5 = plan5.new_state(W.noisy_gaussian(c5))
+        psi5 = init5.clone()
+        n5 = 20
+        w5, _ = timed_steps(torch, plan5, psi5, init5, n5, 5)
+        b5 = sum(plan5.pass_bytes().values())
+        variants["c5_f32_real"] = {"value": c5.npoints * n5 / w5, "ms_per_step": w5 * 1e3 / n5,
+                                   "grid": list(c5.n), "step_effective_GBs": round(b5 * n5 / w5 / 1e9, 1)}
+        log(f"[bench] C5 512x512x256 FP32 real time: {w5 * 1e3 / n5:.3f} ms/step")
+        del plan5, psi5, init5
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -248,46 +272,76 @@ def main():
 # ---------------------------------------------------------------------------
 
 def _short(name):
-    for k in ("k_r2c_z", "k_rows", "k_xmul", "k_c2r_step", "k_c2r_phi", "k_cn_strided", "k_cn_z",
-              "k_reduce", "k_scale", "k_observables", "k_ukern"):
+    for k in ("k_r2c2", "k_rows2", "k_xmul2", "k_c2r_step2", "k_c2r_phi2", "k_r2c_z", "k_rows",
+              "k_xmul", "k_c2r_step", "k_c2r_phi", "k_cn_strided", "k_cn_z", "k_reduce", "k_scale",
+              "k_observables", "k_ukern"):
         if k in name:
             tmpl = name[name.find(k):]
             return tmpl.split("(")[0]
     return name.split("(")[0][:60]
 
 
+def _counter_means(d):
+    """Mean counter value per dispatch by short kernel name, from a rocprofv3
+    --pmc CSV under d (the counter is in KiB for FETCH_SIZE / WRITE_SIZE)."""
+    import csv
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    agg = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            k = _short(r["Kernel_Name"])
+            a = agg.setdefault(k, [0.0, 0])
+            a[0] += float(r["Counter_Value"])
+            a[1] += 1
+    return {k: s / n for k, (s, n) in agg.items()}
+
+
 def summarize(d, name):
-    """Write profiles/<name>.txt (kernel stats) or the traffic JSON from rocprofv3
-    CSV output found under d."""
+    """profiles/<name>.txt from the rocprofv3 --stats output under d."""
     import csv
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     stats = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
-    ctr = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    if stats:
-        rows = list(csv.DictReader(open(stats[0])))
-        out = [f"# rocprofv3 kernel statistics ({name})", f"# source: {os.path.relpath(stats[0], ROOT)}",
-               f"{'kernel':<48} {'calls':>6} {'avg_us':>10} {'total_ms':>10} {'pct':>6}"]
-        for r in rows:
-            out.append(f"{_short(r['Name']):<48} {int(r['Calls']):>6} "
-                       f"{float(r['AverageNs']) / 1e3:>10.2f} {float(r['TotalDurationNs']) / 1e6:>10.3f} "
-                       f"{float(r['Percentage']):>6.2f}")
-        open(os.path.join(ROOT, "profiles", f"{name}.txt"), "w").write("\n".join(out) + "\n")
-        print("\n".join(out))
-    for c in ctr:
-        rows = list(csv.DictReader(open(c)))
-        agg = {}
-        for r in rows:
-            k = _short(r.get("Kernel_Name", r.get("Kernel-Name", "")))
-            cn = r.get("Counter_Name", "")
-            v = float(r.get("Counter_Value", 0))
-            a = agg.setdefault((k, cn), [0.0, 0])
-            a[0] += v
-            a[1] += 1
-        out = {f"{k}|{cn}": {"mean_per_dispatch": s / max(n, 1), "dispatch_rows": n}
-               for (k, cn), (s, n) in agg.items()}
-        path = os.path.join(ROOT, "profiles", f"{name}_counters.json")
-        json.dump({"source": os.path.relpath(c, ROOT), "counters": out}, open(path, "w"), indent=1)
-        print(json.dumps(out, indent=1))
+    rows = list(csv.DictReader(open(stats[0])))
+    out = [f"# rocprofv3 --kernel-trace --stats summary: {name}",
+           f"# {'kernel':<46} {'calls':>6} {'avg_us':>10} {'total_ms':>10} {'pct':>6}"]
+    for r in rows:
+        out.append(f"  {_short(r['Name']):<46} {int(r['Calls']):>6} "
+                   f"{float(r['AverageNs']) / 1e3:>10.2f} {float(r['TotalDurationNs']) / 1e6:>10.3f} "
+                   f"{float(r['Percentage']):>6.2f}")
+    return out
+
+
+def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, header):
+    """HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE, each scaled by the
+    ratio the same counter reads for a plain device copy of known size."""
+    f, w = _counter_means(fetch_dir), _counter_means(write_dir)
+    cf, cw = _counter_means(cfetch_dir), _counter_means(cwrite_dir)
+    ck = "__amd_rocclr_copyBuffer"
+    ffac = cf[ck] * 1024 / copy_bytes
+    wfac = cw[ck] * 1024 / copy_bytes
+    kernels = {}
+    for k in sorted(set(f) & set(w)):
+        if not k.startswith("k_"):
+            continue
+        fb, wb = f[k] * 1024 / ffac, w[k] * 1024 / wfac
+        kernels[k.split("<")[0]] = kernels.get(k.split("<")[0], [])
+        kernels[k.split("<")[0]].append({"variant": k, "fetch_bytes": fb, "write_bytes": wb,
+                                         "hbm_bytes_per_dispatch": fb + wb})
+    rec = {"source_hash": source_hash(), "fetch_scale": ffac, "write_scale": wfac,
+           "copy_bytes": copy_bytes, "header": header,
+           "kernels": {k: max(v, key=lambda e: e["hbm_bytes_per_dispatch"]) for k, v in kernels.items()},
+           "all_variants": kernels}
+    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    lines = [f"# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; separate runs)",
+             f"# {header}",
+             f"# calibration: a {copy_bytes} B device copy read FETCH_SIZE x{ffac:.4f} and WRITE_SIZE x{wfac:.4f} "
+             f"of the bytes moved; kernel values below are divided by these factors",
+             f"# {'kernel':<46} {'fetch_MB':>10} {'write_MB':>10} {'total_MB':>10}"]
+    for k, v in kernels.items():
+        for e in v:
+            lines.append(f"  {e['variant']:<46} {e['fetch_bytes'] / 1e6:>10.2f} {e['write_bytes'] / 1e6:>10.2f} "
+                         f"{e['hbm_bytes_per_dispatch'] / 1e6:>10.2f}")
+    return lines
 
 
 if __name__ == "__main__":

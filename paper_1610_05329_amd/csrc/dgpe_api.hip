@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dgpe.h"
+#include "dgpe.h"
 #include "dgpe_internal.h"
 
 using namespace dgpe;

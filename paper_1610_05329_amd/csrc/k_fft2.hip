@@ -288,14 +288,6 @@ struct Phys2 {
     double dx, dy, dz, cx, cy, cz;
 };
 
-template <typename T>
-__device__ __forceinline__ T trap_v0_2(const Phys2& g, int ix, int iy, int iz) {
-    const T x = T(ix - g.hx) * T(g.dx);
-    const T y = T(iy - g.hy) * T(g.dy);
-    const T z = T(iz - g.hz) * T(g.dz);
-    return T(g.cx) * x * x + T(g.cy) * y * y + T(g.cz) * z * z;
-}
-
 // lines per block of the fused z pass: the state tile (Nz (NB+1) complex) must
 // fit next to the spectral region in 64 KB of LDS
 template <typename T, int R1, int M>
@@ -305,30 +297,31 @@ constexpr int step_nb() {
     return nb;
 }
 
-template <typename T, int R1, int R2, int SZ, bool RC, bool GUARD>
-constexpr int step2_region() {
-    constexpr int M = R1 * R2;
-    constexpr int NB = step_nb<T, R1, M>();
-    constexpr int nseg = (2 * M + SZ - 1) / SZ;
-    constexpr int carries = (2 * nseg * NB * (int)sizeof(cx<cn_acc_t<T, RC>>) + (int)sizeof(cx<T>) - 1) /
-                            (int)sizeof(cx<T>);
-    constexpr int phi = NB * (M + 1);
-    constexpr int a = c2r_region<R1, R2, NB>();
-    return a > carries ? (a > phi ? a : phi) : (carries > phi ? carries : phi);
+template <typename T, int R1, int R2, int SZ>
+constexpr int step2_nb() {
+    return rows_per_block<T, R1, R1 * R2>();
 }
 
-template <typename T, int R1, int R2, int SZ, bool RC, bool GUARD>
+template <typename T, int R1, int R2, int SZ>
 constexpr int step2_threads() {
     constexpr int M = R1 * R2;
-    constexpr int NB = step_nb<T, R1, M>();
+    constexpr int NB = step2_nb<T, R1, R2, SZ>();
     constexpr int nseg = (2 * M + SZ - 1) / SZ;
     constexpr int a = NB * R1, c = NB * nseg;
     constexpr int m = a > c ? a : c;
     return (m + 63) / 64 * 64;
 }
 
-template <typename T, int R1, int R2, int SZ, bool RC, bool GUARD>
-__global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ, RC, GUARD>()))
+// Fused P5 with the state kept in registers: thread (segment s, line b) loads
+// its SZ contiguous points of psi at kernel start (the loads overlap the
+// spectrum load and the inverse FFT), applies the nonlinear phase with Phi
+// from LDS, solves its segment of the z tridiagonal system (carries through
+// LDS) and stores its points.  Lanes: segment fastest, so a wave covers whole
+// lines (each lane one contiguous 16-point run).
+// LDS: region (xin / xb, then Phi pairs) | neighbour and carry arrays |
+// alpha, P, Q tables | twiddles.
+template <typename T, int R1, int R2, int SZ, bool RC>
+__global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     k_c2r_step2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
                 const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
@@ -336,28 +329,47 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ, RC, GUARD>()))
     using A = cn_acc_t<T, RC>;
     constexpr int M = R1 * R2;
     constexpr int Nz = 2 * M;
-    constexpr int NB = step_nb<T, R1, M>();
-    constexpr int ES = NB + 1;
-    constexpr int NT = step2_threads<T, R1, R2, SZ, RC, GUARD>();
-    constexpr int nseg = (Nz + SZ - 1) / SZ;
-    constexpr int REG = step2_region<T, R1, R2, SZ, RC, GUARD>();
+    constexpr int NB = step2_nb<T, R1, R2, SZ>();
+    constexpr int NT = step2_threads<T, R1, R2, SZ>();
+    constexpr int nseg = Nz / SZ;
+    static_assert(Nz % SZ == 0, "full segments only");
+    constexpr int REG = c2r_region<R1, R2, NB>() > NB * (M + 1) ? c2r_region<R1, R2, NB>() : NB * (M + 1);
     __shared__ cx<T> reg[REG];
-    __shared__ cx<T> P[Nz * ES];
-    __shared__ cx<T> stw[M];
-    __shared__ cx<T> sr2c[M + 1];
+    __shared__ cx<A> A1[NB * nseg];
+    __shared__ cx<A> A2[NB * nseg];
+    __shared__ cx<A> ta[Nz];
+    __shared__ cx<A> tp[Nz];
+    __shared__ cx<A> tq[Nz];
     __shared__ cx<A> spe[nseg];
     __shared__ cx<A> sqb[nseg];
+    __shared__ cx<T> stw[M];
+    __shared__ cx<T> sr2c[M + 1];
     const int tid = threadIdx.x;
-    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
-    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
-    for (int i = tid; i < nseg; i += NT) {
-        spe[i] = widen<A>(cntab[TAB_PEND * Nz + i]);
-        sqb[i] = widen<A>(cntab[TAB_QBEG * Nz + i]);
-    }
     const int ngy = Ny / NB;
     const int x = blockIdx.x / ngy;
     const int y0 = (blockIdx.x - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
+    // state segment of this thread, loaded first
+    const int seg = tid % nseg, bl = tid / nseg;
+    const bool act = tid < NB * nseg;
+    const int e0 = seg * SZ;
+    cx<T>* lp = psi + (line0 + bl) * Nz + e0;
+    cx<T> a[SZ];
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < SZ; ++i) a[i] = lp[i];
+    }
+    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
+    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
+    for (int i = tid; i < Nz; i += NT) {
+        ta[i] = widen<A>(cntab[TAB_ALPHA * Nz + i]);
+        tp[i] = widen<A>(cntab[TAB_P * Nz + i]);
+        tq[i] = widen<A>(cntab[TAB_Q * Nz + i]);
+    }
+    for (int i = tid; i < nseg; i += NT) {
+        spe[i] = widen<A>(cntab[TAB_PEND * Nz + i]);
+        sqb[i] = widen<A>(cntab[TAB_QBEG * Nz + i]);
+    }
     cx<T> w[R1];
     c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, spec, (size_t)Nx * Ny, line0, tid, NT);
     __syncthreads();  // reg is rewritten with the Phi pairs
@@ -369,74 +381,56 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ, RC, GUARD>()))
         }
     }
     __syncthreads();
-    // nonlinear step (pre-step density, lazily normalised) into the Psi tile
+    // nonlinear step on the registers (pre-step density, lazily normalised)
     const double sg = sigma ? sigma[0] : 1.0;
     const T sig = T(sg), rs = T(sqrt(sg));
     const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
-    cx<T>* base = psi + line0 * Nz;
-    constexpr int total = NB * Nz;
-    constexpr int LU = 4;
-    for (int g0 = tid; g0 < total; g0 += LU * NT) {
-        cx<T> a[LU];
+    cx<A> v[SZ];
+    if (act) {
+        const T yy = T(y0 + bl - ph.hy) * T(ph.dy);
+        const T xx = T(x - ph.hx) * T(ph.dx);
+        const T vxy = T(ph.cx) * xx * xx + T(ph.cy) * yy * yy;
 #pragma unroll
-        for (int u = 0; u < LU; ++u) {
-            const int g = g0 + u * NT;
-            if (g < total) a[u] = base[g];
-        }
+        for (int i = 0; i < SZ; i += 2) {
+            const cx<T> fv = reg[bl * (M + 1) + ((e0 + i) >> 1)];
 #pragma unroll
-        for (int u = 0; u < LU; ++u) {
-            const int g = g0 + u * NT;
-            if (g < total) {
-                const int b = g / Nz, e = g - b * Nz;
-                const cx<T> fv = reg[b * (M + 1) + (e >> 1)];
-                const T phi = (e & 1) ? fv.y : fv.x;
-                const T n = abs2(a[u]) * sig;
-                const T th = dt * (amp * trap_v0_2<T>(ph, x, y0 + b, e) + gg * n + gdd * phi);
+            for (int h = 0; h < 2; ++h) {
+                const int e = e0 + i + h;
+                const T phi = h ? fv.y : fv.x;
+                const T z = T(e - ph.hz) * T(ph.dz);
+                const T n = abs2(a[i + h]) * sig;
+                const T th = dt * (amp * (vxy + T(ph.cz) * z * z) + gg * n + gdd * phi);
                 cx<T> r;
                 if (ph.imag) {
                     const T f = rs * exp_of(-th);
-                    r = f * a[u];
+                    r = f * a[i + h];
                 } else {
                     T sn, cs;
                     sin_cos(th, &sn, &cs);
                     cs *= rs;
                     sn *= rs;
-                    r = cx<T>{a[u].x * cs + a[u].y * sn, a[u].y * cs - a[u].x * sn};
+                    r = cx<T>{a[i + h].x * cs + a[i + h].y * sn, a[i + h].y * cs - a[i + h].x * sn};
                 }
-                P[e * ES + b] = r;
+                v[i + h] = widen<A>(r);
             }
         }
+        A1[bl * nseg + seg] = v[0];
+        A2[bl * nseg + seg] = v[SZ - 1];
     }
     __syncthreads();
-    // Crank-Nicolson along z: thread -> (line bl, segment seg)
-    cx<A>* dl = reinterpret_cast<cx<A>*>(reg);
-    cx<A>* xf = dl + nseg * NB;
-    const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
-    const int bl = tid % NB;
-    const int seg = tid / NB;
-    const int e0 = seg * SZ;
-    const int cnt = (seg < nseg) ? min(SZ, Nz - e0) : 0;
-    cx<A> v[SZ];
     cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
-    if (cnt > 0) {
-#pragma unroll
-        for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) v[i] = widen<A>(P[(e0 + i) * ES + bl]);
-        if (e0 > 0) left = widen<A>(P[(e0 - 1) * ES + bl]);
-        if (e0 + cnt < Nz) right = widen<A>(P[(e0 + cnt) * ES + bl]);
+    if (act) {
+        if (seg > 0) left = A2[bl * nseg + seg - 1];
+        if (seg + 1 < nseg) right = A1[bl * nseg + seg + 1];
     }
-    cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, cntab + TAB_ALPHA * Nz,
-                                       cntab + TAB_P * Nz, cntab + TAB_Q * Nz, spe, sqb, e0, seg,
-                                       nseg, dl, xf, bl, NB);
-    if (cnt > 0) {
+    __syncthreads();  // neighbour reads done: A2 / A1 become the carries
+    const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
+    // carries indexed [seg * nlines + line] with nlines = NB
+    cn_segment_solve<T, SZ, RC, false>(v, act ? SZ : 0, left, right, kappa, ta, tp, tq, spe, sqb,
+                                       e0, seg, nseg, A2, A1, bl, NB);
+    if (act) {
 #pragma unroll
-        for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = cx<T>{T(v[i].x), T(v[i].y)};
-    }
-    __syncthreads();
-    for (int g = tid; g < total; g += NT) {
-        const int b = g / Nz, e = g - b * Nz;
-        base[g] = P[e * ES + b];
+        for (int i = 0; i < SZ; ++i) lp[i] = cx<T>{T(v[i].x), T(v[i].y)};
     }
 }
 
@@ -550,11 +544,11 @@ bool fast_c2r_phi(const Plan& p, void* phi) {
 template <typename T>
 bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
     const int M = p.n[2] / 2;
-    if (p.lc.seg[2] != 16) return false;
+    if (p.lc.seg[2] != 16 || p.n[2] % 16) return false;
     int nb = 0;
     switch (M) {
 #define DGPE_CASE(A, B) \
-    case A * B: nb = step_nb<T, A, A * B>(); break;
+    case A * B: nb = step2_nb<T, A, B, 16>(); break;
         DGPE_STEP_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
         default: return false;
@@ -567,22 +561,16 @@ bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
              0.5 * p.trap[2] * p.trap[2]};
     const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
     const int blocks = p.n[0] * (p.n[1] / nb);
-    const bool guard = (p.n[2] % 16) != 0;
     switch (M) {
-#define DGPE_LAUNCH(A, B, RCV, GV)                                                                  \
-    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV, GV>), dim3(blocks),                          \
-                       dim3(step2_threads<T, A, B, 16, RCV, GV>()), 0, p.stream, (cx<T>*)psi,      \
+#define DGPE_LAUNCH(A, B, RCV)                                                                      \
+    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV>), dim3(blocks),                              \
+                       dim3(step2_threads<T, A, B, 16>()), 0, p.stream, (cx<T>*)psi,                \
                        (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],                \
                        (const cx<T>*)p.twr2c, tab, kappa, sigma, ph)
-#define DGPE_CASE(A, B)                                   \
-    case A * B:                                           \
-        if (p.imag) {                                     \
-            if (guard) DGPE_LAUNCH(A, B, true, true);     \
-            else DGPE_LAUNCH(A, B, true, false);          \
-        } else {                                          \
-            if (guard) DGPE_LAUNCH(A, B, false, true);    \
-            else DGPE_LAUNCH(A, B, false, false);         \
-        }                                                 \
+#define DGPE_CASE(A, B)                     \
+    case A * B:                             \
+        if (p.imag) DGPE_LAUNCH(A, B, true); \
+        else DGPE_LAUNCH(A, B, false);      \
         return true;
         DGPE_STEP_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
