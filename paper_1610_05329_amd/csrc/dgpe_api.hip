@@ -117,7 +117,9 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
         const bool narrow = f32 && imag;
         const int tmax = narrow ? 1024 : 512;
         const size_t asz = narrow ? 8 : 16;
-        int zb = 64;
+        // measured at 256^3: 32 columns per block (FP32 recurrences) and 16
+        // (FP64 recurrences) overlap loads and solves better than 64
+        int zb = narrow ? 32 : 16;
         auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * L + 2 * nseg) * asz; };
         while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
         if (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget) return false;

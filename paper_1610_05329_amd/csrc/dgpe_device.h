@@ -275,11 +275,20 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
                                                  int nseg, cx<cn_acc_t<T, RC>>* dl,
                                                  cx<cn_acc_t<T, RC>>* xf, int line, int nlines) {
     using A = cn_acc_t<T, RC>;
+    // FP32 recurrences keep the segment's alpha in registers; FP64 ones read it
+    // where it is used (register budget)
+    constexpr bool kPre = sizeof(A) == 4;
     const bool act = cnt > 0;
-    cx<A> al[S];
+    cx<A> al[kPre ? S : 1];
+    if constexpr (kPre) {
 #pragma unroll
-    for (int i = 0; i < S; ++i)
-        if (act && (!GUARD || i < cnt)) al[i] = widen<A>(ta[e0 + i]);
+        for (int i = 0; i < S; ++i)
+            if (act && (!GUARD || i < cnt)) al[i] = widen<A>(ta[e0 + i]);
+    }
+    auto alpha = [&](int i) -> cx<A> {
+        if constexpr (kPre) return al[kPre ? i : 0];
+        else return widen<A>(ta[e0 + i]);
+    };
     // 1. r'_i = u_{i-1} + u_{i+1} + kappa u_i
     cx<A> prev = left;
 #pragma unroll
@@ -299,7 +308,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
-            dcur = kmul<RC>(al[i], dcur + v[i]);
+            dcur = kmul<RC>(alpha(i), dcur + v[i]);
             v[i] = dcur;
         }
     }
@@ -317,7 +326,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
             if (!GUARD || i < cnt) {
-                xcur = v[i] + kmul<RC>(al[i], xcur);
+                xcur = v[i] + kmul<RC>(alpha(i), xcur);
                 v[i] = xcur;
             }
         }
@@ -331,6 +340,94 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
         for (int i = 0; i < S; ++i)
             if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(widen<A>(tq[e0 + i]), c);
     }
+}
+
+}  // namespace dgpe
+
+namespace dgpe {
+
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_up_c(cx<A> v, int d, int width) {
+    return cx<A>{__shfl_up(v.x, d, width), __shfl_up(v.y, d, width)};
+}
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d, int width) {
+    return cx<A>{__shfl_down(v.x, d, width), __shfl_down(v.y, d, width)};
+}
+
+// The same exact segmented Crank-Nicolson solve as cn_segment_solve, for
+// lines whose NSEG segments sit on NSEG consecutive lanes of one wave (segment
+// s on lane s of its group; NSEG a power of two dividing 64; full segments).
+// Neighbour values and carries move by wave shuffles, and the carry
+// recurrences d_end(k) = dtilde_end(k) + Pend(k) d_end(k-1) (and the backward
+// one) are evaluated as an inclusive scan of affine maps x -> a x + b,
+// (a2, b2) o (a1, b1) = (a2 a1, a2 b1 + b2), in log2(NSEG) steps.  No LDS and
+// no barriers.  Tables: alpha, P, Q (length N) and pend, qbeg (per segment).
+template <typename T, int S, int NSEG, bool RC, typename TT, typename TS>
+__device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S],
+                                                      cx<cn_acc_t<T, RC>> kappa, const TT* ta,
+                                                      const TT* tp, const TT* tq, const TS* pend,
+                                                      const TS* qbeg, int seg) {
+    using A = cn_acc_t<T, RC>;
+    const int e0 = seg * S;
+    const cx<A> zero = {A(0), A(0)};
+    // neighbours
+    cx<A> left = shfl_up_c(v[S - 1], 1, NSEG);
+    cx<A> right = shfl_down_c(v[0], 1, NSEG);
+    if (seg == 0) left = zero;
+    if (seg == NSEG - 1) right = zero;
+    // r'_i = u_{i-1} + u_{i+1} + kappa u_i
+    cx<A> prev = left;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const cx<A> cur = v[i];
+        const cx<A> nxt = (i + 1 < S) ? v[(i + 1 < S) ? i + 1 : i] : right;
+        v[i] = prev + nxt + kmul<RC>(kappa, cur);
+        prev = cur;
+    }
+    // forward recurrence from a zero carry
+    cx<A> dcur = zero;
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        dcur = kmul<RC>(widen<A>(ta[e0 + i]), dcur + v[i]);
+        v[i] = dcur;
+    }
+    // inclusive scan over the segments of the line: d_end(s)
+    cx<A> a = widen<A>(pend[seg]), b = dcur;
+#pragma unroll
+    for (int o = 1; o < NSEG; o <<= 1) {
+        const cx<A> ap = shfl_up_c(a, o, NSEG), bp = shfl_up_c(b, o, NSEG);
+        if (seg >= o) {
+            b = b + kmul<RC>(a, bp);
+            a = kmul<RC>(a, ap);
+        }
+    }
+    cx<A> c = shfl_up_c(b, 1, NSEG);
+    if (seg == 0) c = zero;
+#pragma unroll
+    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tp[e0 + i]), c);
+    // back substitution from a zero carry
+    cx<A> xcur = zero;
+#pragma unroll
+    for (int i = S - 1; i >= 0; --i) {
+        xcur = v[i] + kmul<RC>(widen<A>(ta[e0 + i]), xcur);
+        v[i] = xcur;
+    }
+    // scan from the right: true x at the start of each segment
+    a = widen<A>(qbeg[seg]);
+    b = xcur;
+#pragma unroll
+    for (int o = 1; o < NSEG; o <<= 1) {
+        const cx<A> ap = shfl_down_c(a, o, NSEG), bp = shfl_down_c(b, o, NSEG);
+        if (seg + o < NSEG) {
+            b = b + kmul<RC>(a, bp);
+            a = kmul<RC>(a, ap);
+        }
+    }
+    c = shfl_down_c(b, 1, NSEG);
+    if (seg == NSEG - 1) c = zero;
+#pragma unroll
+    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tq[e0 + i]), c);
 }
 
 }  // namespace dgpe

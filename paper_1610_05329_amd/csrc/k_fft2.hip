@@ -315,11 +315,10 @@ constexpr int step2_threads() {
 // Fused P5 with the state kept in registers: thread (segment s, line b) loads
 // its SZ contiguous points of psi at kernel start (the loads overlap the
 // spectrum load and the inverse FFT), applies the nonlinear phase with Phi
-// from LDS, solves its segment of the z tridiagonal system (carries through
-// LDS) and stores its points.  Lanes: segment fastest, so a wave covers whole
-// lines (each lane one contiguous 16-point run).
-// LDS: region (xin / xb, then Phi pairs) | neighbour and carry arrays |
-// alpha, P, Q tables | twiddles.
+// from LDS, solves its segment of the z tridiagonal system (neighbours and
+// carries by wave shuffles) and stores its points.  Lanes: segment fastest, so
+// a wave covers whole lines (each lane one contiguous 16-point run).
+// LDS: region (xin / xb, then Phi pairs) | alpha, P, Q tables | twiddles.
 template <typename T, int R1, int R2, int SZ, bool RC>
 __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     k_c2r_step2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
@@ -333,10 +332,9 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     constexpr int NT = step2_threads<T, R1, R2, SZ>();
     constexpr int nseg = Nz / SZ;
     static_assert(Nz % SZ == 0, "full segments only");
+    static_assert((nseg & (nseg - 1)) == 0 && 64 % nseg == 0, "a line's segments share a wave");
     constexpr int REG = c2r_region<R1, R2, NB>() > NB * (M + 1) ? c2r_region<R1, R2, NB>() : NB * (M + 1);
     __shared__ cx<T> reg[REG];
-    __shared__ cx<A> A1[NB * nseg];
-    __shared__ cx<A> A2[NB * nseg];
     __shared__ cx<A> ta[Nz];
     __shared__ cx<A> tp[Nz];
     __shared__ cx<A> tq[Nz];
@@ -414,20 +412,11 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
                 v[i + h] = widen<A>(r);
             }
         }
-        A1[bl * nseg + seg] = v[0];
-        A2[bl * nseg + seg] = v[SZ - 1];
     }
-    __syncthreads();
-    cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
-    if (act) {
-        if (seg > 0) left = A2[bl * nseg + seg - 1];
-        if (seg + 1 < nseg) right = A1[bl * nseg + seg + 1];
-    }
-    __syncthreads();  // neighbour reads done: A2 / A1 become the carries
+    // Crank-Nicolson along z: the nseg segments of a line are nseg consecutive
+    // lanes of one wave (carries by shuffles)
     const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
-    // carries indexed [seg * nlines + line] with nlines = NB
-    cn_segment_solve<T, SZ, RC, false>(v, act ? SZ : 0, left, right, kappa, ta, tp, tq, spe, sqb,
-                                       e0, seg, nseg, A2, A1, bl, NB);
+    if (act) cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta, tp, tq, spe, sqb, seg);
     if (act) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i) lp[i] = cx<T>{T(v[i].x), T(v[i].y)};
