@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--summary-name", default="")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
     ap.add_argument("--command", default="")
+    ap.add_argument("--traffic-json", action="store_true",
+                    help="also record the traffic as the roofline's counter figures "
+                         "(only for the workload of the JSON line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -140,7 +143,8 @@ def main():
     if args.summarize:
         out = summarize(args.summarize, args.summary_name)
         if args.traffic:
-            out += [""] + summarize_traffic(*args.traffic, 256 << 20, args.summary_name)
+            out += [""] + summarize_traffic(*args.traffic, 256 << 20, args.summary_name,
+                                            TRAFFIC_FILE if args.traffic_json else None)
         out.insert(1, "# command: " + args.command if args.command else "#")
         path = os.path.join(ROOT, "profiles", f"{args.summary_name}.txt")
         open(path, "w").write("\n".join(out) + "\n")
@@ -311,7 +315,7 @@ def summarize(d, name):
     return out
 
 
-def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, header):
+def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, header, json_path):
     """HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE, each scaled by the
     ratio the same counter reads for a plain device copy of known size."""
     f, w = _counter_means(fetch_dir), _counter_means(write_dir)
@@ -331,7 +335,8 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
            "copy_bytes": copy_bytes, "header": header,
            "kernels": {k: max(v, key=lambda e: e["hbm_bytes_per_dispatch"]) for k, v in kernels.items()},
            "all_variants": kernels}
-    json.dump(rec, open(TRAFFIC_FILE, "w"), indent=1)
+    if json_path:
+        json.dump(rec, open(json_path, "w"), indent=1)
     lines = [f"# HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE; separate runs)",
              f"# {header}",
              f"# calibration: a {copy_bytes} B device copy read FETCH_SIZE x{ffac:.4f} and WRITE_SIZE x{wfac:.4f} "

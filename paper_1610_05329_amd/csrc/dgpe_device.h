@@ -56,6 +56,16 @@ __device__ __forceinline__ cx<T> rot90(cx<T> a) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return __umulhi(n, f.m); }
 
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2.  Remap so that each XCD works through one contiguous range
+// of logical tiles: neighbouring tiles that share cache lines then meet in the
+// same L2.  Identity when the grid is not a multiple of 8.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_swizzle(int bid, int nblocks) {
+    if (nblocks % kXcds) return bid;
+    return (bid % kXcds) * (nblocks / kXcds) + bid / kXcds;
+}
+
 // ---------------------------------------------------------------------------
 // small DFTs, forward sign exp(-2 pi i jk/R); INV gives the conjugate kernel
 // ---------------------------------------------------------------------------
@@ -368,8 +378,8 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
                                                       cx<cn_acc_t<T, RC>> kappa, const TT* ta,
                                                       const TT* tp, const TT* tq, const TS* pend,
                                                       const TS* qbeg, int seg) {
+    // ta, tp, tq point at this segment's S entries
     using A = cn_acc_t<T, RC>;
-    const int e0 = seg * S;
     const cx<A> zero = {A(0), A(0)};
     // neighbours
     cx<A> left = shfl_up_c(v[S - 1], 1, NSEG);
@@ -389,7 +399,7 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     cx<A> dcur = zero;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        dcur = kmul<RC>(widen<A>(ta[e0 + i]), dcur + v[i]);
+        dcur = kmul<RC>(widen<A>(ta[i]), dcur + v[i]);
         v[i] = dcur;
     }
     // inclusive scan over the segments of the line: d_end(s)
@@ -405,12 +415,12 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     cx<A> c = shfl_up_c(b, 1, NSEG);
     if (seg == 0) c = zero;
 #pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tp[e0 + i]), c);
+    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tp[i]), c);
     // back substitution from a zero carry
     cx<A> xcur = zero;
 #pragma unroll
     for (int i = S - 1; i >= 0; --i) {
-        xcur = v[i] + kmul<RC>(widen<A>(ta[e0 + i]), xcur);
+        xcur = v[i] + kmul<RC>(widen<A>(ta[i]), xcur);
         v[i] = xcur;
     }
     // scan from the right: true x at the start of each segment
@@ -427,7 +437,7 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     c = shfl_down_c(b, 1, NSEG);
     if (seg == NSEG - 1) c = zero;
 #pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tq[e0 + i]), c);
+    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tq[i]), c);
 }
 
 }  // namespace dgpe

@@ -62,8 +62,9 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
     }
     const cx<A> kappa = narrow_tab<A>(kappa64);
     const int ncb = C >> logZB;
-    const int o = blockIdx.x / ncb;
-    const int c0 = (blockIdx.x - o * ncb) << logZB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int o = bid / ncb;
+    const int c0 = (bid - o * ncb) << logZB;
     const int cl = tid & (ZB - 1);
     const int seg = tid >> logZB;
     const int e0 = seg * S;

@@ -63,7 +63,8 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 
 // ---------------------------------------------------------------------------
 // P3: FFT along x (stride Ny) of NB adjacent columns at one kz, multiply by
-// U_R/Nt (quarter table indexed by |kx|, |ky|), inverse FFT along x.
+// U_R/Nt (table [kz][|kx|][ky]: each entry read once per step), inverse FFT
+// along x.
 // Lanes: b fastest (NB columns), t < R1 threads per column.
 // ---------------------------------------------------------------------------
 template <typename T, int R1, int R2>
@@ -72,14 +73,16 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
             const T* __restrict__ ukern) {
     constexpr int L = R1 * R2;  // Nx
     constexpr int NB = rows_per_block<T, R1, L>();
+    constexpr int NT = NB * R1;
     __shared__ cx<T> xb[NB * L];
     __shared__ cx<T> stw[L];
     const int tid = threadIdx.x;
     const int b = tid % NB, t = tid / NB;
-    for (int i = tid; i < L; i += NB * R1) stw[i] = tw[i];
+    for (int i = tid; i < L; i += NT) stw[i] = tw[i];
     const int ngy = Ny / NB;
-    const int kz = blockIdx.x / ngy;
-    const int y0 = (blockIdx.x - kz * ngy) * NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int kz = bid / ngy;
+    const int y0 = (bid - kz * ngy) * NB;
     cx<T>* base = spec + (size_t)kz * L * Ny + y0 + b;
     cx<T> v[R2];
 #pragma unroll
@@ -95,16 +98,13 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 #pragma unroll
         for (int n = 0; n < R1; ++n) w[n] = xb[(t * R1 + n) * NB + b];
         rdft<T, R1, false>(w);
-        // w[k1] = X[kx = t + R2 k1]
-        const int hx = L / 2 + 1, hy = Ny / 2 + 1;
-        const int ky0 = y0 + b;
-        const int ky = min(ky0, Ny - ky0);
-        const T* urow = ukern + (size_t)kz * hx * hy + ky;
+        // w[k1] = X[kx = t + R2 k1]; the kernel is even in kx: table [kz][|kx|][ky]
+        const T* ucol = ukern + (size_t)kz * (L / 2 + 1) * Ny + y0 + b;
 #pragma unroll
         for (int k = 0; k < R1; ++k) {
             const int kx0 = t + R2 * k;
             const int kx = min(kx0, L - kx0);
-            w[k] = urow[(size_t)kx * hy] * w[k];
+            w[k] = ucol[(size_t)kx * Ny] * w[k];
         }
         // inverse: the layout of w is the phase-A layout of the (R2, R1) split
         rdft<T, R1, true>(w);
@@ -154,8 +154,9 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     for (int i = tid; i < M; i += NT) stw[i] = twz[i];
     for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
     const int ngy = Ny / NB;
-    const int x = blockIdx.x / ngy;
-    const int y0 = (blockIdx.x - x * ngy) * NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x = bid / ngy;
+    const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
     const T sig = sigma ? T(sigma[0]) : T(1);
     const cx<T>* base = psi + (line0 + b) * (2 * M);
@@ -196,14 +197,14 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 // Front half of the z inverse transform for NB lines: load X_k (k <= M),
 // form Z_j, two-factor inverse FFT.  On return thread (b, t < R2) holds
 // z_m = (Phi_{2m}, Phi_{2m+1}) for m = t + R2 k in w[k] (already / Nt).
-// xin needs NB * (M + 2) entries, xb NB * R2 * (R1 + 1); they may alias.
+// xin needs NB * (M + 1) entries, xb NB * R2 * (R1 + 1); they may alias.
 template <typename T, int R1, int R2, int NB>
 __device__ __forceinline__ void c2r_front2(cx<T> (&w)[R1], cx<T>* xin, cx<T>* xb, const cx<T>* stw,
                                            const cx<T>* sr2c, const cx<T>* __restrict__ spec,
                                            size_t plane, size_t line0, int tid, int nthr) {
     constexpr int M = R1 * R2;
     constexpr int SB = R2 * (R1 + 1);
-    constexpr int SI = M + 2;
+    constexpr int SI = M + 1;
     for (int g = tid; g < (M + 1) * NB; g += nthr) {
         const int k = g / NB, bl = g - k * NB;
         xin[bl * SI + k] = spec[(size_t)k * plane + line0 + bl];
@@ -245,7 +246,7 @@ __device__ __forceinline__ void c2r_front2(cx<T> (&w)[R1], cx<T>* xin, cx<T>* xb
 template <int R1, int R2, int NB>
 constexpr int c2r_region() {  // complex entries of the xin / xb region
     constexpr int M = R1 * R2;
-    return NB * (M + 2) > NB * R2 * (R1 + 1) ? NB * (M + 2) : NB * R2 * (R1 + 1);
+    return NB * (M + 1) > NB * R2 * (R1 + 1) ? NB * (M + 1) : NB * R2 * (R1 + 1);
 }
 
 // Phi to a real [Nx][Ny][Nz] buffer.
@@ -263,8 +264,9 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     for (int i = tid; i < M; i += NT) stw[i] = twz[i];
     for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
     const int ngy = Ny / NB;
-    const int x = blockIdx.x / ngy;
-    const int y0 = (blockIdx.x - x * ngy) * NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x = bid / ngy;
+    const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
     cx<T> w[R1];
     c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, spec, (size_t)Nx * Ny, line0, tid, NT);
@@ -333,19 +335,24 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     constexpr int nseg = Nz / SZ;
     static_assert(Nz % SZ == 0, "full segments only");
     static_assert((nseg & (nseg - 1)) == 0 && 64 % nseg == 0, "a line's segments share a wave");
-    constexpr int REG = c2r_region<R1, R2, NB>() > NB * (M + 1) ? c2r_region<R1, R2, NB>() : NB * (M + 1);
+    // Phi pairs at m + m/8 and table entries at e + e/SZ: with segment-fastest
+    // lanes these reads then fall in distinct LDS banks
+    constexpr int PS = M + M / 8 + 1;
+    constexpr int TS = Nz + Nz / SZ;
+    constexpr int REG = c2r_region<R1, R2, NB>() > NB * PS ? c2r_region<R1, R2, NB>() : NB * PS;
     __shared__ cx<T> reg[REG];
-    __shared__ cx<A> ta[Nz];
-    __shared__ cx<A> tp[Nz];
-    __shared__ cx<A> tq[Nz];
+    __shared__ cx<A> ta[TS];
+    __shared__ cx<A> tp[TS];
+    __shared__ cx<A> tq[TS];
     __shared__ cx<A> spe[nseg];
     __shared__ cx<A> sqb[nseg];
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
     const int tid = threadIdx.x;
     const int ngy = Ny / NB;
-    const int x = blockIdx.x / ngy;
-    const int y0 = (blockIdx.x - x * ngy) * NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x = bid / ngy;
+    const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
     // state segment of this thread, loaded first
     const int seg = tid % nseg, bl = tid / nseg;
@@ -360,9 +367,10 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     for (int i = tid; i < M; i += NT) stw[i] = twz[i];
     for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
     for (int i = tid; i < Nz; i += NT) {
-        ta[i] = widen<A>(cntab[TAB_ALPHA * Nz + i]);
-        tp[i] = widen<A>(cntab[TAB_P * Nz + i]);
-        tq[i] = widen<A>(cntab[TAB_Q * Nz + i]);
+        const int ip = i + i / SZ;
+        ta[ip] = widen<A>(cntab[TAB_ALPHA * Nz + i]);
+        tp[ip] = widen<A>(cntab[TAB_P * Nz + i]);
+        tq[ip] = widen<A>(cntab[TAB_Q * Nz + i]);
     }
     for (int i = tid; i < nseg; i += NT) {
         spe[i] = widen<A>(cntab[TAB_PEND * Nz + i]);
@@ -375,7 +383,10 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
         const int t = tid % R1, b = tid / R1;
         if (tid < NB * R1 && t < R2) {
 #pragma unroll
-            for (int k = 0; k < R1; ++k) reg[b * (M + 1) + t + R2 * k] = w[k];
+            for (int k = 0; k < R1; ++k) {
+                const int m = t + R2 * k;
+                reg[b * PS + m + (m >> 3)] = w[k];
+            }
         }
     }
     __syncthreads();
@@ -390,7 +401,8 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
         const T vxy = T(ph.cx) * xx * xx + T(ph.cy) * yy * yy;
 #pragma unroll
         for (int i = 0; i < SZ; i += 2) {
-            const cx<T> fv = reg[bl * (M + 1) + ((e0 + i) >> 1)];
+            const int m = (e0 + i) >> 1;
+            const cx<T> fv = reg[bl * PS + m + (m >> 3)];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int e = e0 + i + h;
@@ -416,7 +428,8 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     // Crank-Nicolson along z: the nseg segments of a line are nseg consecutive
     // lanes of one wave (carries by shuffles)
     const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
-    if (act) cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta, tp, tq, spe, sqb, seg);
+    const int tb = seg * (SZ + 1);
+    if (act) cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
     if (act) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i) lp[i] = cx<T>{T(v[i].x), T(v[i].y)};
