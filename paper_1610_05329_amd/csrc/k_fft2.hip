@@ -314,13 +314,77 @@ constexpr int step2_threads() {
     return (m + 63) / 64 * 64;
 }
 
-// Fused P5 with the state kept in registers: thread (segment s, line b) loads
-// its SZ contiguous points of psi at kernel start (the loads overlap the
-// spectrum load and the inverse FFT), applies the nonlinear phase with Phi
-// from LDS, solves its segment of the z tridiagonal system (neighbours and
-// carries by wave shuffles) and stores its points.  Lanes: segment fastest, so
-// a wave covers whole lines (each lane one contiguous 16-point run).
-// LDS: region (xin / xb, then Phi pairs) | alpha, P, Q tables | twiddles.
+// 16-byte units of the state: two FP32 or one FP64 complex values
+template <typename T>
+struct unit16;
+template <>
+struct unit16<float> {
+    using type = float4;
+};
+template <>
+struct unit16<double> {
+    using type = double2;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_unit(const cx<T>* p, cx<T>* out) {
+    const auto q = *reinterpret_cast<const typename unit16<T>::type*>(p);
+    if constexpr (sizeof(T) == 4) {
+        out[0] = cx<T>{q.x, q.y};
+        out[1] = cx<T>{q.z, q.w};
+    } else {
+        out[0] = cx<T>{q.x, q.y};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_unit(cx<T>* p, const cx<T>* in) {
+    typename unit16<T>::type q;
+    if constexpr (sizeof(T) == 4) {
+        q = float4{in[0].x, in[0].y, in[1].x, in[1].y};
+    } else {
+        q = double2{in[0].x, in[0].y};
+    }
+    *reinterpret_cast<typename unit16<T>::type*>(p) = q;
+}
+
+// Orders the LDS accesses of one wave (no cross-wave synchronisation)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Staging geometry of the fused z pass.  A wave owns LPW = 64 / nseg whole
+// lines; its state moves between HBM and registers in 16-byte units with
+// consecutive lanes on consecutive addresses, and is transposed to and from
+// the segment layout of the tridiagonal solve through the LDS rows that held
+// the wave's Phi (free once the nonlinear step has read them), KR lines at a
+// time.  A staged line is Nz values with one unit of padding after each
+// segment, so that the segment-wise 16-byte accesses spread over the banks.
+template <typename T, int R1, int R2, int SZ>
+struct Step2Geom {
+    static constexpr int M = R1 * R2;
+    static constexpr int Nz = 2 * M;
+    static constexpr int nseg = Nz / SZ;
+    static constexpr int LPW = 64 / nseg;
+    static constexpr int U = 16 / (int)sizeof(cx<T>);
+    static constexpr int NU = SZ / U;  // units per lane
+    static constexpr int PS = M + M / 8 + 1;
+    static constexpr int SL = Nz + nseg * U;
+    static constexpr int fit = (LPW * PS) / SL;
+    static constexpr int KR = fit >= LPW ? LPW : fit >= 8 ? 8 : fit >= 4 ? 4 : fit >= 2 ? 2 : 1;
+    static constexpr int JR = KR * Nz / (64 * U);  // unit loads per lane and round
+};
+
+// Fused P5 with the state kept in registers: each wave loads its lines
+// (coalesced 16-byte units) at kernel start, so the loads overlap the spectrum
+// load and the inverse FFT; the nonlinear phase is applied in that layout with
+// Phi from LDS; the values are then transposed through LDS to the segment
+// layout (lane = segment, segment fastest) for the z tridiagonal solve
+// (neighbours and carries by wave shuffles), and back for coalesced stores.
+// LDS: region (xin / xb, then Phi pairs, then the staging) | alpha, P, Q tables
+// | twiddles.
 template <typename T, int R1, int R2, int SZ, bool RC>
 __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     k_c2r_step2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
@@ -328,19 +392,21 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
                 const double* __restrict__ sigma, Phys2 ph) {
     using A = cn_acc_t<T, RC>;
-    constexpr int M = R1 * R2;
-    constexpr int Nz = 2 * M;
+    using G = Step2Geom<T, R1, R2, SZ>;
+    constexpr int M = G::M, Nz = G::Nz, nseg = G::nseg, LPW = G::LPW, U = G::U, NU = G::NU;
+    constexpr int PS = G::PS, SL = G::SL, KR = G::KR, JR = G::JR;
     constexpr int NB = step2_nb<T, R1, R2, SZ>();
     constexpr int NT = step2_threads<T, R1, R2, SZ>();
-    constexpr int nseg = Nz / SZ;
-    static_assert(Nz % SZ == 0, "full segments only");
+    static_assert(Nz % SZ == 0 && SZ % U == 0, "full segments of whole units");
     static_assert((nseg & (nseg - 1)) == 0 && 64 % nseg == 0, "a line's segments share a wave");
-    // Phi pairs at m + m/8 and table entries at e + e/SZ: with segment-fastest
-    // lanes these reads then fall in distinct LDS banks
-    constexpr int PS = M + M / 8 + 1;
+    static_assert(NB % LPW == 0 && NB * nseg <= NT, "whole waves of lines");
+    static_assert(LPW % KR == 0 && (KR * Nz) % (64 * U) == 0 && KR * SL <= LPW * PS,
+                  "staging rounds of whole unit loads inside the wave's Phi rows");
+    static_assert((LPW * PS) % U == 0, "16-byte aligned staging");
+    // Phi pairs at m + m/8 and table entries at e + e/SZ (bank spread)
     constexpr int TS = Nz + Nz / SZ;
     constexpr int REG = c2r_region<R1, R2, NB>() > NB * PS ? c2r_region<R1, R2, NB>() : NB * PS;
-    __shared__ cx<T> reg[REG];
+    __shared__ __align__(16) cx<T> reg[REG];
     __shared__ cx<A> ta[TS];
     __shared__ cx<A> tp[TS];
     __shared__ cx<A> tq[TS];
@@ -349,20 +415,20 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const bool act = wv * LPW < NB;  // wave-uniform
     const int ngy = Ny / NB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int x = bid / ngy;
     const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
-    // state segment of this thread, loaded first
-    const int seg = tid % nseg, bl = tid / nseg;
-    const bool act = tid < NB * nseg;
-    const int e0 = seg * SZ;
-    cx<T>* lp = psi + (line0 + bl) * Nz + e0;
+    // the wave's LPW lines are LPW * Nz consecutive values; unit j of this lane
+    // holds values (j * 64 + lane) * U + u
+    cx<T>* wp = psi + (line0 + (size_t)wv * LPW) * Nz;
     cx<T> a[SZ];
     if (act) {
 #pragma unroll
-        for (int i = 0; i < SZ; ++i) a[i] = lp[i];
+        for (int j = 0; j < NU; ++j) load_unit<T>(wp + (j * 64 + lane) * U, a + j * U);
     }
     for (int i = tid; i < M; i += NT) stw[i] = twz[i];
     for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
@@ -390,38 +456,64 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
         }
     }
     __syncthreads();
-    // nonlinear step on the registers (pre-step density, lazily normalised)
+    if (!act) return;  // no barrier follows
+    // nonlinear step in the load layout (pre-step density, lazily normalised)
     const double sg = sigma ? sigma[0] : 1.0;
     const T sig = T(sg), rs = T(sqrt(sg));
     const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
+    const T xx = T(x - ph.hx) * T(ph.dx);
+    const T vx = T(ph.cx) * xx * xx;
+    const cx<T>* prow = reg + wv * LPW * PS;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+        const int c0 = (j * 64 + lane) * U;
+        const int lw = c0 / Nz, e0 = c0 % Nz;
+        const T yy = T(y0 + wv * LPW + lw - ph.hy) * T(ph.dy);
+        const T vxy = vx + T(ph.cy) * yy * yy;
+        const int m = e0 >> 1;
+        const cx<T> fv = prow[lw * PS + m + (m >> 3)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int e = e0 + u;
+            const T phi = (e & 1) ? fv.y : fv.x;
+            const T z = T(e - ph.hz) * T(ph.dz);
+            cx<T>& q = a[j * U + u];
+            const T n = abs2(q) * sig;
+            const T th = dt * (amp * (vxy + T(ph.cz) * z * z) + gg * n + gdd * phi);
+            if constexpr (RC) {  // real coefficients: imaginary time
+                q = (rs * exp_of(-th)) * q;
+            } else {
+                T sn, cs;
+                sin_cos(th, &sn, &cs);
+                cs *= rs;
+                sn *= rs;
+                q = cx<T>{q.x * cs + q.y * sn, q.y * cs - q.x * sn};
+            }
+        }
+    }
+    // to the segment layout, KR lines per round, through this wave's Phi rows
+    cx<T>* stg = reg + wv * LPW * PS;
+    const int seg = lane % nseg, sl = lane / nseg;
     cx<A> v[SZ];
-    if (act) {
-        const T yy = T(y0 + bl - ph.hy) * T(ph.dy);
-        const T xx = T(x - ph.hx) * T(ph.dx);
-        const T vxy = T(ph.cx) * xx * xx + T(ph.cy) * yy * yy;
 #pragma unroll
-        for (int i = 0; i < SZ; i += 2) {
-            const int m = (e0 + i) >> 1;
-            const cx<T> fv = reg[bl * PS + m + (m >> 3)];
+    for (int r = 0; r < LPW / KR; ++r) {
+        wave_sync();  // previous reads of the rows done
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int e = e0 + i + h;
-                const T phi = h ? fv.y : fv.x;
-                const T z = T(e - ph.hz) * T(ph.dz);
-                const T n = abs2(a[i + h]) * sig;
-                const T th = dt * (amp * (vxy + T(ph.cz) * z * z) + gg * n + gdd * phi);
-                cx<T> r;
-                if (ph.imag) {
-                    const T f = rs * exp_of(-th);
-                    r = f * a[i + h];
-                } else {
-                    T sn, cs;
-                    sin_cos(th, &sn, &cs);
-                    cs *= rs;
-                    sn *= rs;
-                    r = cx<T>{a[i + h].x * cs + a[i + h].y * sn, a[i + h].y * cs - a[i + h].x * sn};
-                }
-                v[i + h] = widen<A>(r);
+        for (int jj = 0; jj < JR; ++jj) {
+            const int j = r * JR + jj;
+            const int c = (j * 64 + lane) * U - r * KR * Nz;
+            const int e = c % Nz;
+            store_unit<T>(stg + (c / Nz) * SL + e + (e / SZ) * U, a + j * U);
+        }
+        wave_sync();
+        if (sl / KR == r) {
+            const cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                cx<T> t2[U];
+                load_unit<T>(sp + j * U, t2);
+#pragma unroll
+                for (int u = 0; u < U; ++u) v[j * U + u] = widen<A>(t2[u]);
             }
         }
     }
@@ -429,10 +521,31 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     // lanes of one wave (carries by shuffles)
     const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
     const int tb = seg * (SZ + 1);
-    if (act) cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
-    if (act) {
+    cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
+    // back to the load layout and out
 #pragma unroll
-        for (int i = 0; i < SZ; ++i) lp[i] = cx<T>{T(v[i].x), T(v[i].y)};
+    for (int r = 0; r < LPW / KR; ++r) {
+        wave_sync();
+        if (sl / KR == r) {
+            cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
+#pragma unroll
+            for (int j = 0; j < NU; ++j) {
+                cx<T> t2[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) t2[u] = cx<T>{T(v[j * U + u].x), T(v[j * U + u].y)};
+                store_unit<T>(sp + j * U, t2);
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int jj = 0; jj < JR; ++jj) {
+            const int j = r * JR + jj;
+            const int c = (j * 64 + lane) * U - r * KR * Nz;
+            const int e = c % Nz;
+            cx<T> t2[U];
+            load_unit<T>(stg + (c / Nz) * SL + e + (e / SZ) * U, t2);
+            store_unit<T>(wp + (j * 64 + lane) * U, t2);
+        }
     }
 }
 
