@@ -115,12 +115,14 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
         // FP32 imaginary time keeps FP32 recurrences (1024-thread blocks); FP64
         // and real-time recurrences are FP64 (512-thread blocks)
         const bool narrow = f32 && imag;
-        const int tmax = narrow ? 1024 : 512;
+        // FP64 recurrences hold ~150 VGPRs (3 waves per SIMD): blocks of at
+        // most 256 threads keep 3 blocks per CU resident
+        const int tmax = narrow ? 1024 : 256;
         const size_t asz = narrow ? 8 : 16;
         // measured at 256^3: 32 columns per block (FP32 recurrences) and 16
         // (FP64 recurrences) overlap loads and solves better than 64
         int zb = narrow ? 32 : 16;
-        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * L + 2 * nseg) * asz; };
+        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * nseg * (S + 1) + 2 * nseg) * asz; };
         while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
         if (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget) return false;
         lc->seg[axis] = S;

@@ -41,8 +41,74 @@ template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
 template <typename T>
 __device__ __forceinline__ T abs2(cx<T> a) { return a.x * a.x + a.y * a.y; }
-__device__ __forceinline__ void sin_cos(float x, float* s, float* c) { sincosf(x, s, c); }
-__device__ __forceinline__ void sin_cos(double x, double* s, double* c) { sincos(x, s, c); }
+// sin and cos of a phase angle.  Cody-Waite reduction in FP64: k = rint(2x/pi),
+// r = (x - k P1) - k P2 with P1 = pi/2 rounded to 33 significant bits (k P1
+// exact for |k| < 2^20) and P2 = pi/2 - P1; then the Taylor series of sin and
+// cos on |r| <= pi/4 and the quadrant's exchange and signs.  Truncation: the
+// first omitted term is below 2e-9 (FP32: through r^9 and r^10) and below 1e-19
+// (FP64: through r^17 and r^18) relative to the result's scale.
+namespace detail {
+constexpr double kTwoOverPi = 0.6366197723675814;
+constexpr double kPio2Hi = 1.5707963267341256;   // 0x3FF921FB54400000
+constexpr double kPio2Lo = 6.077100506506192e-11;
+
+__device__ __forceinline__ double reduce_pio2(double x, int* q) {
+    const double k = rint(x * kTwoOverPi);
+    *q = int(k) & 3;
+    return fma(-k, kPio2Lo, fma(-k, kPio2Hi, x));
+}
+
+template <typename T>
+__device__ __forceinline__ void quadrant(int q, T sr, T cr, T* s, T* c) {
+    const T a = (q & 1) ? cr : sr;   // sin(r + q pi/2) up to sign
+    const T b = (q & 1) ? sr : cr;   // cos(r + q pi/2) up to sign
+    *s = (q & 2) ? -a : a;
+    *c = ((q + 1) & 2) ? -b : b;
+}
+}  // namespace detail
+
+__device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
+    int q;
+    const float r = float(detail::reduce_pio2(double(x), &q));
+    const float r2 = r * r;
+    // sin r = r (1 - r^2/3! + r^4/5! - r^6/7! + r^8/9!)
+    float ps = 1.0f / 362880.0f;
+    ps = fmaf(ps, r2, -1.0f / 5040.0f);
+    ps = fmaf(ps, r2, 1.0f / 120.0f);
+    ps = fmaf(ps, r2, -1.0f / 6.0f);
+    const float sr = fmaf(r * r2, ps, r);
+    // cos r = 1 - r^2/2! + r^4/4! - ... - r^10/10!
+    float pc = -1.0f / 3628800.0f;
+    pc = fmaf(pc, r2, 1.0f / 40320.0f);
+    pc = fmaf(pc, r2, -1.0f / 720.0f);
+    pc = fmaf(pc, r2, 1.0f / 24.0f);
+    pc = fmaf(pc, r2, -0.5f);
+    const float cr = fmaf(r2, pc, 1.0f);
+    detail::quadrant(q, sr, cr, s, c);
+}
+
+__device__ __forceinline__ void sin_cos(double x, double* s, double* c) {
+    int q;
+    const double r = detail::reduce_pio2(x, &q);
+    const double r2 = r * r;
+    // odd Taylor terms through r^17, even ones through r^18: coefficients
+    // (-1)^n / (2n+1)! and (-1)^n / (2n)!
+    constexpr double S[9] = {1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0,
+                             -1.0 / 39916800.0, 1.0 / 6227020800.0, -1.0 / 1307674368000.0,
+                             1.0 / 355687428096000.0};
+    constexpr double C[10] = {1.0, -0.5, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0,
+                              -1.0 / 3628800.0, 1.0 / 479001600.0, -1.0 / 87178291200.0,
+                              1.0 / 20922789888000.0, -1.0 / 6402373705728000.0};
+    double ps = S[8];
+#pragma unroll
+    for (int i = 7; i >= 1; --i) ps = fma(ps, r2, S[i]);
+    const double sr = fma(r * r2, ps, r);
+    double pc = C[9];
+#pragma unroll
+    for (int i = 8; i >= 1; --i) pc = fma(pc, r2, C[i]);
+    const double cr = fma(r2, pc, 1.0);
+    detail::quadrant(q, sr, cr, s, c);
+}
 __device__ __forceinline__ float exp_of(float x) { return expf(x); }
 __device__ __forceinline__ double exp_of(double x) { return exp(x); }
 // multiply by -i (forward) or +i (inverse)
@@ -273,15 +339,30 @@ using cn_acc_t = typename std::conditional<RC, T, double>::type;
 
 template <typename A, typename T>
 __device__ __forceinline__ cx<A> widen(cx<T> v) { return cx<A>{A(v.x), A(v.y)}; }
+// conversion between the arithmetic type and the segment values' type.  The
+// segment values stay in the arithmetic type: rounding the real-time FP64
+// intermediates (r', d) to FP32 between the passes was measured to lose norm
+// steadily (1e-8 per step at 128^3), unlike one rounding of the result
+template <typename V, typename A>
+__device__ __forceinline__ cx<V> to_store(cx<A> v) { return cx<V>{V(v.x), V(v.y)}; }
 
-template <typename T, int S, bool RC, bool GUARD, typename TT>
-__device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], int cnt,
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_up_c(cx<A> v, int d, int width) {
+    return cx<A>{__shfl_up(v.x, d, width), __shfl_up(v.y, d, width)};
+}
+template <typename A>
+__device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d, int width) {
+    return cx<A>{__shfl_down(v.x, d, width), __shfl_down(v.y, d, width)};
+}
+
+template <typename T, int S, bool RC, bool GUARD, typename TT, typename VS>
+__device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
                                                  cx<cn_acc_t<T, RC>> left,
                                                  cx<cn_acc_t<T, RC>> right,
                                                  cx<cn_acc_t<T, RC>> kappa, const cx<TT>* ta,
                                                  const cx<TT>* tp, const cx<TT>* tq,
                                                  const cx<cn_acc_t<T, RC>>* pend,
-                                                 const cx<cn_acc_t<T, RC>>* qbeg, int e0, int seg,
+                                                 const cx<cn_acc_t<T, RC>>* qbeg, int tb, int seg,
                                                  int nseg, cx<cn_acc_t<T, RC>>* dl,
                                                  cx<cn_acc_t<T, RC>>* xf, int line, int nlines) {
     using A = cn_acc_t<T, RC>;
@@ -293,51 +374,53 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
     if constexpr (kPre) {
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (act && (!GUARD || i < cnt)) al[i] = widen<A>(ta[e0 + i]);
+            if (act && (!GUARD || i < cnt)) al[i] = widen<A>(ta[tb + i]);
     }
     auto alpha = [&](int i) -> cx<A> {
         if constexpr (kPre) return al[kPre ? i : 0];
-        else return widen<A>(ta[e0 + i]);
+        else return widen<A>(ta[tb + i]);
     };
     // 1. r'_i = u_{i-1} + u_{i+1} + kappa u_i
     cx<A> prev = left;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
-            const cx<A> cur = v[i];
+            const cx<A> cur = widen<A>(v[i]);
             cx<A> nxt = right;
             if (i + 1 < S) {
-                if (!GUARD || i + 1 < cnt) nxt = v[(i + 1 < S) ? i + 1 : i];
+                if (!GUARD || i + 1 < cnt) nxt = widen<A>(v[(i + 1 < S) ? i + 1 : i]);
             }
-            v[i] = prev + nxt + kmul<RC>(kappa, cur);
+            v[i] = to_store<VS>(prev + nxt + kmul<RC>(kappa, cur));
             prev = cur;
         }
     }
-    // 2. forward recurrence, zero carry
-    cx<A> dcur = {A(0), A(0)};
+    // 2. forward recurrence, zero carry (threads without a segment read no table)
+    if (act) {
+        cx<A> dcur = {A(0), A(0)};
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-        if (!GUARD || i < cnt) {
-            dcur = kmul<RC>(alpha(i), dcur + v[i]);
-            v[i] = dcur;
+        for (int i = 0; i < S; ++i) {
+            if (!GUARD || i < cnt) {
+                dcur = kmul<RC>(alpha(i), dcur + widen<A>(v[i]));
+                v[i] = to_store<VS>(dcur);
+            }
         }
+        dl[seg * nlines + line] = dcur;
     }
-    if (act) dl[seg * nlines + line] = dcur;
     __syncthreads();
     if (act) {
-        // 3. true d_{e0-1} from the segments on the left
+        // 3. true d before the segment's first point, from the segments on the left
         cx<A> c = {A(0), A(0)};
         for (int k = 0; k < seg; ++k) c = dl[k * nlines + line] + kmul<RC>(pend[k], c);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(widen<A>(tp[e0 + i]), c);
+            if (!GUARD || i < cnt) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c));
         // 4. back substitution, zero carry
         cx<A> xcur = {A(0), A(0)};
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
             if (!GUARD || i < cnt) {
-                xcur = v[i] + kmul<RC>(alpha(i), xcur);
-                v[i] = xcur;
+                xcur = widen<A>(v[i]) + kmul<RC>(alpha(i), xcur);
+                v[i] = to_store<VS>(xcur);
             }
         }
         xf[seg * nlines + line] = xcur;
@@ -348,7 +431,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
         for (int k = nseg - 1; k > seg; --k) c = xf[k * nlines + line] + kmul<RC>(qbeg[k], c);
 #pragma unroll
         for (int i = 0; i < S; ++i)
-            if (!GUARD || i < cnt) v[i] = v[i] + kmul<RC>(widen<A>(tq[e0 + i]), c);
+            if (!GUARD || i < cnt) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[tb + i]), c));
     }
 }
 
@@ -356,14 +439,6 @@ __device__ __forceinline__ void cn_segment_solve(cx<cn_acc_t<T, RC>> (&v)[S], in
 
 namespace dgpe {
 
-template <typename A>
-__device__ __forceinline__ cx<A> shfl_up_c(cx<A> v, int d, int width) {
-    return cx<A>{__shfl_up(v.x, d, width), __shfl_up(v.y, d, width)};
-}
-template <typename A>
-__device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d, int width) {
-    return cx<A>{__shfl_down(v.x, d, width), __shfl_down(v.y, d, width)};
-}
 
 // The same exact segmented Crank-Nicolson solve as cn_segment_solve, for
 // lines whose NSEG segments sit on NSEG consecutive lanes of one wave (segment
@@ -373,8 +448,8 @@ __device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d, int width) {
 // one) are evaluated as an inclusive scan of affine maps x -> a x + b,
 // (a2, b2) o (a1, b1) = (a2 a1, a2 b1 + b2), in log2(NSEG) steps.  No LDS and
 // no barriers.  Tables: alpha, P, Q (length N) and pend, qbeg (per segment).
-template <typename T, int S, int NSEG, bool RC, typename TT, typename TS>
-__device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S],
+template <typename T, int S, int NSEG, bool RC, typename TT, typename TS, typename VS>
+__device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
                                                       cx<cn_acc_t<T, RC>> kappa, const TT* ta,
                                                       const TT* tp, const TT* tq, const TS* pend,
                                                       const TS* qbeg, int seg) {
@@ -382,25 +457,25 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     using A = cn_acc_t<T, RC>;
     const cx<A> zero = {A(0), A(0)};
     // neighbours
-    cx<A> left = shfl_up_c(v[S - 1], 1, NSEG);
-    cx<A> right = shfl_down_c(v[0], 1, NSEG);
+    cx<A> left = widen<A>(shfl_up_c(v[S - 1], 1, NSEG));
+    cx<A> right = widen<A>(shfl_down_c(v[0], 1, NSEG));
     if (seg == 0) left = zero;
     if (seg == NSEG - 1) right = zero;
     // r'_i = u_{i-1} + u_{i+1} + kappa u_i
     cx<A> prev = left;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        const cx<A> cur = v[i];
-        const cx<A> nxt = (i + 1 < S) ? v[(i + 1 < S) ? i + 1 : i] : right;
-        v[i] = prev + nxt + kmul<RC>(kappa, cur);
+        const cx<A> cur = widen<A>(v[i]);
+        const cx<A> nxt = (i + 1 < S) ? widen<A>(v[(i + 1 < S) ? i + 1 : i]) : right;
+        v[i] = to_store<VS>(prev + nxt + kmul<RC>(kappa, cur));
         prev = cur;
     }
     // forward recurrence from a zero carry
     cx<A> dcur = zero;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        dcur = kmul<RC>(widen<A>(ta[i]), dcur + v[i]);
-        v[i] = dcur;
+        dcur = kmul<RC>(widen<A>(ta[i]), dcur + widen<A>(v[i]));
+        v[i] = to_store<VS>(dcur);
     }
     // inclusive scan over the segments of the line: d_end(s)
     cx<A> a = widen<A>(pend[seg]), b = dcur;
@@ -415,13 +490,15 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     cx<A> c = shfl_up_c(b, 1, NSEG);
     if (seg == 0) c = zero;
 #pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tp[i]), c);
-    // back substitution from a zero carry
+    for (int i = 0; i < S; ++i) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c));
+    // back substitution from a zero carry.  FP64 factors are read again here
+    // rather than kept live since the forward pass (64 registers)
+    if constexpr (sizeof(A) == 8) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     cx<A> xcur = zero;
 #pragma unroll
     for (int i = S - 1; i >= 0; --i) {
-        xcur = v[i] + kmul<RC>(widen<A>(ta[i]), xcur);
-        v[i] = xcur;
+        xcur = widen<A>(v[i]) + kmul<RC>(widen<A>(ta[i]), xcur);
+        v[i] = to_store<VS>(xcur);
     }
     // scan from the right: true x at the start of each segment
     a = widen<A>(qbeg[seg]);
@@ -437,7 +514,7 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     c = shfl_down_c(b, 1, NSEG);
     if (seg == NSEG - 1) c = zero;
 #pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tq[i]), c);
+    for (int i = 0; i < S; ++i) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[i]), c));
 }
 
 }  // namespace dgpe

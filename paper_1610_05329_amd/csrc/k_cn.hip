@@ -33,7 +33,9 @@ CnTab tab_of(const void* base, int N) {
 template <typename A>
 __device__ __forceinline__ cx<A> narrow_tab(cx<double> v) { return cx<A>{A(v.x), A(v.y)}; }
 
-// LDS: A1[nseg*ZB] | A2[nseg*ZB] (arithmetic type) | alpha[L] | P[L] | Q[L] | pend | qbeg
+// LDS: A1[nseg*ZB] | A2[nseg*ZB] (arithmetic type) | alpha | P | Q (each
+// nseg*(S+1): segment s at s*(S+1), so that the segments of a wave read
+// distinct banks) | pend | qbeg
 template <typename T, int S, bool RC, bool GUARD>
 __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2 : kMaxThreads)
     k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab tg,
@@ -46,15 +48,17 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
     const int nsl = nseg << logZB;
     cx<A>* A1 = reinterpret_cast<cx<A>*>(smem_raw);
     cx<A>* A2 = A1 + nsl;
+    const int TL = nseg * (S + 1);
     cx<A>* ta = A2 + nsl;
-    cx<A>* tp = ta + L;
-    cx<A>* tq = tp + L;
-    cx<A>* pe = tq + L;
+    cx<A>* tp = ta + TL;
+    cx<A>* tq = tp + TL;
+    cx<A>* pe = tq + TL;
     cx<A>* qb = pe + nseg;
     for (int i = tid; i < L; i += nthr) {
-        ta[i] = narrow_tab<A>(tg.a[i]);
-        tp[i] = narrow_tab<A>(tg.p[i]);
-        tq[i] = narrow_tab<A>(tg.q[i]);
+        const int ip = i + i / S;
+        ta[ip] = narrow_tab<A>(tg.a[i]);
+        tp[ip] = narrow_tab<A>(tg.p[i]);
+        tq[ip] = narrow_tab<A>(tg.q[i]);
     }
     for (int i = tid; i < nseg; i += nthr) {
         pe[i] = narrow_tab<A>(tg.pend[i]);
@@ -91,13 +95,13 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
         if (seg + 1 < nseg) right = A1[(seg + 1) * ZB + cl];
     }
     __syncthreads();  // neighbour reads done: A2 becomes the forward carries, A1 the backward ones
-    cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta, tp, tq, pe, qb, e0, seg,
+    cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta, tp, tq, pe, qb, seg * (S + 1), seg,
                                       nseg, A2, A1, cl, ZB);
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
-            const cx<T> o = {T(v[i].x), T(v[i].y)};
+            const cx<T> o = to_store<T>(v[i]);
             base[(size_t)(e0 + i) * C] = o;
             acc += double(abs2(o));
         }
@@ -153,7 +157,7 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = cx<T>{T(v[i].x), T(v[i].y)};
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = to_store<T>(v[i]);
     }
     __syncthreads();
     for (int g = tid; g < total; g += nthr) {
@@ -191,7 +195,7 @@ hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
     const cx<double> kappa = {k.re, k.im};
     const int blocks = cn_strided_blocks(p, axis);
     const size_t asz = (p.imag ? sizeof(T) : sizeof(double)) * 2;
-    const size_t sm = (size_t)(2 * threads + 3 * L + 2 * nseg) * asz;
+    const size_t sm = (size_t)(2 * threads + 3 * nseg * (S + 1) + 2 * nseg) * asz;
     const bool guard = (L % S) != 0;
 #define DGPE_CN(SV, RCV, GV)                                                                      \
     hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV>), dim3(blocks), dim3(threads), sm, p.stream, \

@@ -145,7 +145,9 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     constexpr int M = R1 * R2;
     constexpr int NB = rows_per_block<T, R1, M>();
     constexpr int NT = NB * R1;
-    constexpr int SB = R2 * (R1 + 1);  // >= M + 1
+    // >= M + 1; odd, so that the post-processing reads (line fastest) spread
+    // over the banks
+    constexpr int SB = R2 * (R1 + 1) + 1;
     __shared__ cx<T> xb[NB * SB];
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
@@ -532,7 +534,7 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
             for (int j = 0; j < NU; ++j) {
                 cx<T> t2[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) t2[u] = cx<T>{T(v[j * U + u].x), T(v[j * U + u].y)};
+                for (int u = 0; u < U; ++u) t2[u] = to_store<T>(v[j * U + u]);
                 store_unit<T>(sp + j * U, t2);
             }
         }

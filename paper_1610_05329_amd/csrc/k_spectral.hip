@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = cx<T>{T(v[i].x), T(v[i].y)};
+            if (!GUARD || i < cnt) P[(e0 + i) * ES + bl] = to_store<T>(v[i]);
     }
     __syncthreads();
     for (int g = tid; g < total; g += nthr) {

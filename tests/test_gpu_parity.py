@@ -90,6 +90,37 @@ def test_steps_match_oracle(dg, torch_mod, shape, real_time, prec):
     assert err < TOL[prec]
 
 
+LONG_SHAPES = [
+    ((512, 12, 16), (0.05, 0.4, 0.35)),
+    ((16, 384, 12), (0.4, 0.06, 0.4)),
+    ((12, 16, 768), (0.4, 0.35, 0.03)),
+    ((12, 16, 512), (0.4, 0.35, 0.04)),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("real_time", [False, True], ids=["imag", "real"])
+@pytest.mark.parametrize("shape", LONG_SHAPES, ids=lambda s: "x".join(map(str, s[0])))
+def test_long_lines_match_oracle(dg, torch_mod, shape, real_time, prec):
+    """Lines of 384 to 768 points: 24 to 48 segments per line in the sweeps
+    (segment carries across several waves, segment counts that are not powers
+    of two) and the generic spectral passes for lengths without a compiled
+    two-factor split."""
+    n, d = shape
+    steps = 4
+    cfg = W.Config("t", n, d, 0.002, (1.0, 1.1, 1.3), 20.0, 8.0, not real_time, steps, noise=1e-3, seed=9)
+    _say(f"long lines {n} {'real' if real_time else 'imag'} {prec}")
+    psi0 = W.noisy_gaussian(cfg)
+    plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=real_time, dtype=_dtype(torch_mod, prec))
+    psi = plan.new_state(psi0)
+    plan.step(psi, steps)
+    got = psi.cpu().numpy().astype(np.complex128)
+    ref = O.evolve(O.Params.from_config(cfg), psi0, steps)
+    err = _rel(got, ref)
+    _say(f"  rel L2 {err:.3e}")
+    assert err < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_observables_match_oracle(dg, torch_mod, prec):
     n, d = (32, 36, 48), (0.3, 0.3, 0.25)
