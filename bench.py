@@ -134,7 +134,7 @@ def main():
                          "(only for the workload of the JSON line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--adjoint-steps", type=int, default=40)
     ap.add_argument("--workload", choices=["C3", "C5"], default="C3",
                     help="configuration of --profile-run (the JSON line always uses C3)")
