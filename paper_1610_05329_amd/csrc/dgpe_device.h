@@ -17,6 +17,7 @@ namespace dgpe {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct alignas(2 * sizeof(T)) cx {
+    using value_type = T;
     T x, y;
 };
 
@@ -339,6 +340,30 @@ using cn_acc_t = typename std::conditional<RC, T, double>::type;
 
 template <typename A, typename T>
 __device__ __forceinline__ cx<A> widen(cx<T> v) { return cx<A>{A(v.x), A(v.y)}; }
+// Small per-block tables (twiddles, Thomas factors) in registers: every load
+// issued first, staged in LDS after the block's other loads are in flight.
+template <typename V, int N, int NT>
+struct TabRegs {
+    static constexpr int R = (N + NT - 1) / NT;
+    V v[R];
+};
+
+template <typename V, int N, int NT, typename S>
+__device__ __forceinline__ void tab_issue(TabRegs<V, N, NT>& r, const S* __restrict__ src, int tid) {
+#pragma unroll
+    for (int u = 0; u < TabRegs<V, N, NT>::R; ++u) r.v[u] = src[min(tid + u * NT, N - 1)];
+}
+
+// Stages a TabRegs in LDS at dst[index(i)].  Every thread writes (threads past
+// the end repeat the last entry, with its own value): a conditional write would
+// let the compiler move the load down into the branch, and the wait for it
+// would then also wait for the state loads issued after it.
+template <typename V, int N, int NT, typename D, typename F>
+__device__ __forceinline__ void tab_stage(const TabRegs<V, N, NT>& r, D* dst, int tid, F index) {
+#pragma unroll
+    for (int u = 0; u < TabRegs<V, N, NT>::R; ++u) dst[index(min(tid + u * NT, N - 1))] = widen<typename D::value_type>(r.v[u]);
+}
+
 // conversion between the arithmetic type and the segment values' type.  The
 // segment values stay in the arithmetic type: rounding the real-time FP64
 // intermediates (r', d) to FP32 between the passes was measured to lose norm

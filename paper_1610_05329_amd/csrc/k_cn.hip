@@ -54,16 +54,12 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
     cx<A>* tq = tp + TL;
     cx<A>* pe = tq + TL;
     cx<A>* qb = pe + nseg;
-    for (int i = tid; i < L; i += nthr) {
-        const int ip = i + i / S;
-        ta[ip] = narrow_tab<A>(tg.a[i]);
-        tp[ip] = narrow_tab<A>(tg.p[i]);
-        tq[ip] = narrow_tab<A>(tg.q[i]);
-    }
-    for (int i = tid; i < nseg; i += nthr) {
-        pe[i] = narrow_tab<A>(tg.pend[i]);
-        qb[i] = narrow_tab<A>(tg.qbeg[i]);
-    }
+    // First round of the table loads (one entry of each table per thread,
+    // clamped: the writes below are unconditional so the loads stay ahead of
+    // the state loads; see tab_stage), then the state, then staging.
+    const int i0 = min(tid, L - 1), s0 = min(tid, nseg - 1);
+    const cx<double> a0 = tg.a[i0], p0 = tg.p[i0], q0 = tg.q[i0];
+    const cx<double> pe0 = tg.pend[s0], qb0 = tg.qbeg[s0];
     const cx<A> kappa = narrow_tab<A>(kappa64);
     const int ncb = C >> logZB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -78,6 +74,21 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
 #pragma unroll
     for (int i = 0; i < S; ++i)
         if (!GUARD || i < cnt) v[i] = widen<A>(base[(size_t)(e0 + i) * C]);
+    ta[i0 + i0 / S] = narrow_tab<A>(a0);
+    tp[i0 + i0 / S] = narrow_tab<A>(p0);
+    tq[i0 + i0 / S] = narrow_tab<A>(q0);
+    pe[s0] = narrow_tab<A>(pe0);
+    qb[s0] = narrow_tab<A>(qb0);
+    for (int i = tid + nthr; i < L; i += nthr) {  // lines longer than the block
+        const int ip = i + i / S;
+        ta[ip] = narrow_tab<A>(tg.a[i]);
+        tp[ip] = narrow_tab<A>(tg.p[i]);
+        tq[ip] = narrow_tab<A>(tg.q[i]);
+    }
+    for (int i = tid + nthr; i < nseg; i += nthr) {
+        pe[i] = narrow_tab<A>(tg.pend[i]);
+        qb[i] = narrow_tab<A>(tg.qbeg[i]);
+    }
     cx<A> lastv = v[S - 1];
     if (GUARD) {
 #pragma unroll

@@ -34,15 +34,17 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     __shared__ cx<T> stw[L];
     const int tid = threadIdx.x;
     const int t = tid % R1, b = tid / R1;
-    for (int i = tid; i < L; i += NB * R1) stw[i] = tw[i];
     const int row = blockIdx.x * NB + b;
     const bool ok = row < nrows;
-    cx<T>* base = spec + (size_t)row * L;
+    // twiddles, then the rows (rows past the end read the last row, unused):
+    // every load in flight before the first wait
+    TabRegs<cx<T>, L, NB * R1> rtw;
+    tab_issue(rtw, tw, tid);
+    cx<T>* base = spec + (size_t)min(row, nrows - 1) * L;
     cx<T> v[R2];
-    if (ok) {
 #pragma unroll
-        for (int n = 0; n < R2; ++n) v[n] = base[t + R1 * n];
-    }
+    for (int n = 0; n < R2; ++n) v[n] = base[t + R1 * n];
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
     __syncthreads();
     if (ok) {
         rdft<T, R2, INV>(v);
@@ -78,15 +80,28 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     __shared__ cx<T> stw[L];
     const int tid = threadIdx.x;
     const int b = tid % NB, t = tid / NB;
-    for (int i = tid; i < L; i += NT) stw[i] = tw[i];
     const int ngy = Ny / NB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int kz = bid / ngy;
     const int y0 = (bid - kz * ngy) * NB;
+    // twiddles, the spectrum columns and the kernel values, all in flight
+    // before the first wait
+    TabRegs<cx<T>, L, NT> rtw;
+    tab_issue(rtw, tw, tid);
     cx<T>* base = spec + (size_t)kz * L * Ny + y0 + b;
     cx<T> v[R2];
 #pragma unroll
     for (int n = 0; n < R2; ++n) v[n] = base[(size_t)(t + R1 * n) * Ny];
+    // after the forward FFT thread t < R2 holds X[kx = t + R2 k]; the kernel is
+    // even in kx: table [kz][|kx|][ky] (threads t >= R2 read t = R2 - 1's)
+    const T* ucol = ukern + (size_t)kz * (L / 2 + 1) * Ny + y0 + b;
+    T uk[R1];
+#pragma unroll
+    for (int k = 0; k < R1; ++k) {
+        const int kx0 = min(t, R2 - 1) + R2 * k;
+        uk[k] = ucol[(size_t)min(kx0, L - kx0) * Ny];
+    }
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
     __syncthreads();
     rdft<T, R2, false>(v);
     twiddle_phase<T, R2, false>(v, t, stw);
@@ -98,14 +113,8 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 #pragma unroll
         for (int n = 0; n < R1; ++n) w[n] = xb[(t * R1 + n) * NB + b];
         rdft<T, R1, false>(w);
-        // w[k1] = X[kx = t + R2 k1]; the kernel is even in kx: table [kz][|kx|][ky]
-        const T* ucol = ukern + (size_t)kz * (L / 2 + 1) * Ny + y0 + b;
 #pragma unroll
-        for (int k = 0; k < R1; ++k) {
-            const int kx0 = t + R2 * k;
-            const int kx = min(kx0, L - kx0);
-            w[k] = ucol[(size_t)kx * Ny] * w[k];
-        }
+        for (int k = 0; k < R1; ++k) w[k] = uk[k] * w[k];
         // inverse: the layout of w is the phase-A layout of the (R2, R1) split
         rdft<T, R1, true>(w);
         twiddle_phase<T, R1, true>(w, t, stw);
@@ -153,22 +162,30 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     __shared__ cx<T> sr2c[M + 1];
     const int tid = threadIdx.x;
     const int t = tid % R1, b = tid / R1;
-    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
-    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
     const int ngy = Ny / NB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int x = bid / ngy;
     const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
-    const T sig = sigma ? T(sigma[0]) : T(1);
+    // twiddles, then the state: every load in flight before the first wait
+    TabRegs<cx<T>, M, NT> rtw;
+    TabRegs<cx<T>, M + 1, NT> rr2;
+    tab_issue(rtw, twz, tid);
+    tab_issue(rr2, twr2c, tid);
     const cx<T>* base = psi + (line0 + b) * (2 * M);
-    cx<T> v[R2];
+    cx<T> pa[R2], pc[R2];
 #pragma unroll
     for (int n = 0; n < R2; ++n) {
         const int j = t + R1 * n;
-        const cx<T> a = base[2 * j], c = base[2 * j + 1];
-        v[n] = cx<T>{abs2(a) * sig, abs2(c) * sig};
+        pa[n] = base[2 * j];
+        pc[n] = base[2 * j + 1];
     }
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
+    tab_stage(rr2, sr2c, tid, [](int i) { return i; });
+    const T sig = sigma ? T(sigma[0]) : T(1);
+    cx<T> v[R2];
+#pragma unroll
+    for (int n = 0; n < R2; ++n) v[n] = cx<T>{abs2(pa[n]) * sig, abs2(pc[n]) * sig};
     __syncthreads();
     rdft<T, R2, false>(v);
     twiddle_phase<T, R2, false>(v, t, stw);
@@ -196,22 +213,52 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     }
 }
 
-// Front half of the z inverse transform for NB lines: load X_k (k <= M),
-// form Z_j, two-factor inverse FFT.  On return thread (b, t < R2) holds
-// z_m = (Phi_{2m}, Phi_{2m+1}) for m = t + R2 k in w[k] (already / Nt).
-// xin needs NB * (M + 1) entries, xb NB * R2 * (R1 + 1); they may alias.
+// Spectrum values of the z inverse transform for NB lines, in registers: the
+// (M+1) x NB block of X_k (k <= M) read in NSP rounds of NT threads, every load
+// issued before any is waited for.  Out-of-range slots of the last round read
+// the block's last value (in bounds) and are not staged.
+template <typename T, int M, int NB, int NT>
+struct SpecRegs {
+    static constexpr int N = ((M + 1) * NB + NT - 1) / NT;
+    cx<T> v[N];
+};
+
+template <typename T, int M, int NB, int NT>
+__device__ __forceinline__ void c2r_issue_loads(SpecRegs<T, M, NB, NT>& r,
+                                                const cx<T>* __restrict__ spec, size_t plane,
+                                                size_t line0, int tid) {
+    constexpr int total = (M + 1) * NB;
+#pragma unroll
+    for (int u = 0; u < SpecRegs<T, M, NB, NT>::N; ++u) {
+        const int g = min(tid + u * NT, total - 1);
+        const int k = g / NB, bl = g - k * NB;
+        r.v[u] = spec[(size_t)k * plane + line0 + bl];
+    }
+}
+
+template <typename T, int M, int NB, int NT>
+__device__ __forceinline__ void c2r_stage(const SpecRegs<T, M, NB, NT>& r, cx<T>* xin, int tid) {
+    constexpr int total = (M + 1) * NB;
+    constexpr int SI = M + 1;
+#pragma unroll
+    for (int u = 0; u < SpecRegs<T, M, NB, NT>::N; ++u) {
+        const int g = min(tid + u * NT, total - 1);  // see tab_stage
+        const int k = g / NB, bl = g - k * NB;
+        xin[bl * SI + k] = r.v[u];
+    }
+}
+
+// Front half of the z inverse transform for NB lines, from X_k (k <= M) staged
+// in xin (c2r_stage, then a barrier): form Z_j, two-factor inverse FFT.  On
+// return thread (b, t < R2) holds z_m = (Phi_{2m}, Phi_{2m+1}) for
+// m = t + R2 k in w[k] (already / Nt).  xin needs NB * (M + 1) entries, xb
+// NB * R2 * (R1 + 1); they may alias.
 template <typename T, int R1, int R2, int NB>
 __device__ __forceinline__ void c2r_front2(cx<T> (&w)[R1], cx<T>* xin, cx<T>* xb, const cx<T>* stw,
-                                           const cx<T>* sr2c, const cx<T>* __restrict__ spec,
-                                           size_t plane, size_t line0, int tid, int nthr) {
+                                           const cx<T>* sr2c, int tid) {
     constexpr int M = R1 * R2;
     constexpr int SB = R2 * (R1 + 1);
     constexpr int SI = M + 1;
-    for (int g = tid; g < (M + 1) * NB; g += nthr) {
-        const int k = g / NB, bl = g - k * NB;
-        xin[bl * SI + k] = spec[(size_t)k * plane + line0 + bl];
-    }
-    __syncthreads();
     const int t = tid % R1, b = tid / R1;
     const bool act = tid < NB * R1;
     cx<T> v[R2];
@@ -245,6 +292,7 @@ __device__ __forceinline__ void c2r_front2(cx<T> (&w)[R1], cx<T>* xin, cx<T>* xb
     }
 }
 
+
 template <int R1, int R2, int NB>
 constexpr int c2r_region() {  // complex entries of the xin / xb region
     constexpr int M = R1 * R2;
@@ -263,15 +311,23 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
     const int tid = threadIdx.x;
-    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
-    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
     const int ngy = Ny / NB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int x = bid / ngy;
     const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
+    TabRegs<cx<T>, M, NT> rtw;
+    TabRegs<cx<T>, M + 1, NT> rr2;
+    SpecRegs<T, M, NB, NT> rs;
+    tab_issue(rtw, twz, tid);
+    tab_issue(rr2, twr2c, tid);
+    c2r_issue_loads(rs, spec, (size_t)Nx * Ny, line0, tid);
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
+    tab_stage(rr2, sr2c, tid, [](int i) { return i; });
+    c2r_stage(rs, reg, tid);
+    __syncthreads();
     cx<T> w[R1];
-    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, spec, (size_t)Nx * Ny, line0, tid, NT);
+    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, tid);
     const int t = tid % R1, b = tid / R1;
     if (t < R2) {
         cx<T>* out = reinterpret_cast<cx<T>*>(phi + (line0 + b) * (2 * M));
@@ -424,28 +480,42 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     const int x = bid / ngy;
     const int y0 = (bid - x * ngy) * NB;
     const size_t line0 = (size_t)x * Ny + y0;
+    // Every global load of the block is issued before the first wait: tables
+    // and the spectrum block first, the state last, so that staging the former
+    // in LDS leaves the state loads in flight through the inverse FFT.
+    TabRegs<cx<T>, M, NT> rtw;
+    TabRegs<cx<T>, M + 1, NT> rr2;
+    TabRegs<cx<double>, Nz, NT> rta, rtp, rtq;
+    TabRegs<cx<double>, nseg, NT> rpe, rqb;
+    SpecRegs<T, M, NB, NT> rsp;
+    tab_issue(rtw, twz, tid);
+    tab_issue(rr2, twr2c, tid);
+    tab_issue(rta, cntab + TAB_ALPHA * Nz, tid);
+    tab_issue(rtp, cntab + TAB_P * Nz, tid);
+    tab_issue(rtq, cntab + TAB_Q * Nz, tid);
+    tab_issue(rpe, cntab + TAB_PEND * Nz, tid);
+    tab_issue(rqb, cntab + TAB_QBEG * Nz, tid);
+    c2r_issue_loads(rsp, spec, (size_t)Nx * Ny, line0, tid);
     // the wave's LPW lines are LPW * Nz consecutive values; unit j of this lane
-    // holds values (j * 64 + lane) * U + u
-    cx<T>* wp = psi + (line0 + (size_t)wv * LPW) * Nz;
+    // holds values (j * 64 + lane) * U + u (waves without lines load the last
+    // wave's, unused, to keep the load sequence uniform)
+    cx<T>* wp = psi + (line0 + (size_t)min(wv * LPW, NB - LPW)) * Nz;
     cx<T> a[SZ];
-    if (act) {
 #pragma unroll
-        for (int j = 0; j < NU; ++j) load_unit<T>(wp + (j * 64 + lane) * U, a + j * U);
-    }
-    for (int i = tid; i < M; i += NT) stw[i] = twz[i];
-    for (int i = tid; i <= M; i += NT) sr2c[i] = twr2c[i];
-    for (int i = tid; i < Nz; i += NT) {
-        const int ip = i + i / SZ;
-        ta[ip] = widen<A>(cntab[TAB_ALPHA * Nz + i]);
-        tp[ip] = widen<A>(cntab[TAB_P * Nz + i]);
-        tq[ip] = widen<A>(cntab[TAB_Q * Nz + i]);
-    }
-    for (int i = tid; i < nseg; i += NT) {
-        spe[i] = widen<A>(cntab[TAB_PEND * Nz + i]);
-        sqb[i] = widen<A>(cntab[TAB_QBEG * Nz + i]);
-    }
+    for (int j = 0; j < NU; ++j) load_unit<T>(wp + (j * 64 + lane) * U, a + j * U);
+    const auto ident = [](int i) { return i; };
+    const auto padded = [](int i) { return i + i / SZ; };
+    tab_stage(rtw, stw, tid, ident);
+    tab_stage(rr2, sr2c, tid, ident);
+    tab_stage(rta, ta, tid, padded);
+    tab_stage(rtp, tp, tid, padded);
+    tab_stage(rtq, tq, tid, padded);
+    tab_stage(rpe, spe, tid, ident);
+    tab_stage(rqb, sqb, tid, ident);
+    c2r_stage(rsp, reg, tid);
+    __syncthreads();
     cx<T> w[R1];
-    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, spec, (size_t)Nx * Ny, line0, tid, NT);
+    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, tid);
     __syncthreads();  // reg is rewritten with the Phi pairs
     {
         const int t = tid % R1, b = tid / R1;
