@@ -380,6 +380,37 @@ __device__ __forceinline__ cx<A> shfl_down_c(cx<A> v, int d, int width) {
     return cx<A>{__shfl_down(v.x, d, width), __shfl_down(v.y, d, width)};
 }
 
+// Carry of the exact segmented Thomas solve from the published segment ends
+// b_k = buf[k * nlines + line] and the segment products m_k, over k in
+// [k0, k1): c = b_k + m_k c taken in increasing k (forward: the true d before
+// segment k1) or decreasing k (backward: the true x after segment k0 - 1).
+// CH segments per round (4 in FP32, 2 in FP64: registers), their LDS reads
+// issued together.
+template <typename A, bool RC, bool REV>
+__device__ __forceinline__ cx<A> carry_chain(const cx<A>* buf, const cx<A>* m, int k0, int k1,
+                                             int nlines, int line) {
+    constexpr int CH = sizeof(A) == 4 ? 4 : 2;
+    cx<A> c = {A(0), A(0)};
+    const int n = k1 - k0;
+    int r = 0;
+    for (; r + CH <= n; r += CH) {
+        cx<A> bv[CH], mv[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            const int k = REV ? k1 - 1 - (r + q) : k0 + r + q;
+            bv[q] = buf[k * nlines + line];
+            mv[q] = m[k];
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) c = bv[q] + kmul<RC>(mv[q], c);
+    }
+    for (; r < n; ++r) {
+        const int k = REV ? k1 - 1 - r : k0 + r;
+        c = buf[k * nlines + line] + kmul<RC>(m[k], c);
+    }
+    return c;
+}
+
 template <typename T, int S, bool RC, bool GUARD, typename TT, typename VS>
 __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
                                                  cx<cn_acc_t<T, RC>> left,
@@ -434,8 +465,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
     __syncthreads();
     if (act) {
         // 3. true d before the segment's first point, from the segments on the left
-        cx<A> c = {A(0), A(0)};
-        for (int k = 0; k < seg; ++k) c = dl[k * nlines + line] + kmul<RC>(pend[k], c);
+        cx<A> c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
 #pragma unroll
         for (int i = 0; i < S; ++i)
             if (!GUARD || i < cnt) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c));
@@ -452,8 +482,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
     }
     __syncthreads();
     if (act) {
-        cx<A> c = {A(0), A(0)};
-        for (int k = nseg - 1; k > seg; --k) c = xf[k * nlines + line] + kmul<RC>(qbeg[k], c);
+        cx<A> c = carry_chain<A, RC, true>(xf, qbeg, seg + 1, nseg, nlines, line);
 #pragma unroll
         for (int i = 0; i < S; ++i)
             if (!GUARD || i < cnt) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[tb + i]), c));
