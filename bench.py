@@ -136,8 +136,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--adjoint-steps", type=int, default=40)
-    ap.add_argument("--workload", choices=["C3", "C5"], default="C3",
-                    help="configuration of --profile-run (the JSON line always uses C3)")
+    ap.add_argument("--workload", choices=["C3", "C5", "ADJ"], default="C3",
+                    help="configuration of --profile-run (the JSON line always uses C3); ADJ = "
+                         "the FP32 real-time adjoint variant of C3 (--steps forward steps, "
+                         "checkpoints every 10)")
     args = ap.parse_args()
 
     if args.summarize:
@@ -170,6 +172,17 @@ def main():
         log(f"copy calibration: 5 copies of {n * 4} bytes")
         return
 
+    if args.profile_run and args.workload == "ADJ":
+        cfg = W.CONFIGS["C3"]
+        plan_a = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True,
+                         dtype=torch.complex64)
+        psia = plan_a.new_state(W.noisy_gaussian(cfg))
+        amp = np.ones(args.steps + 1)
+        plan_a.adjoint(psia, amp[:3], ckpt_every=2)  # warm-up
+        plan_a.adjoint(psia, amp, ckpt_every=10)
+        torch.cuda.synchronize()
+        log("[bench] adjoint profile run done")
+        return
     cfg = W.CONFIGS[args.workload if args.profile_run else "C3"]
     log(f"[bench] workload {cfg.n} {'imaginary' if cfg.imag else 'real'} time; preparing seeded state")
     psi0 = W.noisy_gaussian(cfg)

@@ -486,8 +486,9 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
             DGPE_HIP(launch_cn_z<T>(p, lam, true));
             DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
             DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));
-            DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part));
-            DGPE_HIP(launch_reduce(p, part, r2c_blocks(p), 4, sums + (size_t)n * 4, nullptr));
+            int nbs = 0;
+            DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part, &nbs));
+            DGPE_HIP(launch_reduce(p, part, nbs, 4, sums + (size_t)n * 4, nullptr));
             DGPE_HIP(launch_rows<T>(p, false));
             DGPE_HIP(launch_xmul<T>(p));
             DGPE_HIP(launch_rows<T>(p, true));

@@ -340,6 +340,125 @@ using cn_acc_t = typename std::conditional<RC, T, double>::type;
 
 template <typename A, typename T>
 __device__ __forceinline__ cx<A> widen(cx<T> v) { return cx<A>{A(v.x), A(v.y)}; }
+// 16-byte units of the state: two FP32 or one FP64 complex values
+template <typename T>
+struct unit16;
+template <>
+struct unit16<float> {
+    using type = float4;
+};
+template <>
+struct unit16<double> {
+    using type = double2;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_unit(const cx<T>* p, cx<T>* out) {
+    const auto q = *reinterpret_cast<const typename unit16<T>::type*>(p);
+    if constexpr (sizeof(T) == 4) {
+        out[0] = cx<T>{q.x, q.y};
+        out[1] = cx<T>{q.z, q.w};
+    } else {
+        out[0] = cx<T>{q.x, q.y};
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_unit(cx<T>* p, const cx<T>* in) {
+    typename unit16<T>::type q;
+    if constexpr (sizeof(T) == 4) {
+        q = float4{in[0].x, in[0].y, in[1].x, in[1].y};
+    } else {
+        q = double2{in[0].x, in[0].y};
+    }
+    *reinterpret_cast<typename unit16<T>::type*>(p) = q;
+}
+
+// Orders the LDS accesses of one wave (no cross-wave synchronisation)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
+// A wave's LPW = 64 / nseg whole lines of Nz values (LPW * Nz consecutive
+// values in HBM) in two layouts: the load layout (lane l holds the 16-byte
+// units j * 64 + l, coalesced) and the segment layout (lane = segment of SZ
+// consecutive points, the nseg segments of a line on consecutive lanes).  The
+// transposes go through the wave's own LDS staging area, KR lines per round;
+// a staged line is Nz values with one 16-byte unit of padding after each
+// segment (the segment-wise accesses then spread over the banks).
+template <typename T, int Nz, int SZ, int KR>
+struct WaveLines {
+    static constexpr int nseg = Nz / SZ;
+    static constexpr int LPW = 64 / nseg;
+    static constexpr int U = 16 / (int)sizeof(cx<T>);
+    static constexpr int NU = SZ / U;           // units per lane
+    static constexpr int SL = Nz + nseg * U;    // staged line
+    static constexpr int JR = KR * Nz / (64 * U);  // unit loads per lane and round
+    static_assert(LPW % KR == 0 && JR * 64 * U == KR * Nz, "rounds of whole unit loads");
+
+    __device__ static int unit_pos(int j, int lane, int r) {
+        const int c = (j * 64 + lane) * U - r * KR * Nz;
+        const int e = c % Nz;
+        return (c / Nz) * SL + e + (e / SZ) * U;
+    }
+
+    template <typename A>
+    __device__ static void to_segments(cx<T>* stg, const cx<T> (&a)[SZ], cx<A> (&v)[SZ], int lane) {
+        const int seg = lane % nseg, sl = lane / nseg;
+#pragma unroll
+        for (int r = 0; r < LPW / KR; ++r) {
+            wave_sync();  // earlier reads of the staging area done
+#pragma unroll
+            for (int jj = 0; jj < JR; ++jj) {
+                const int j = r * JR + jj;
+                store_unit<T>(stg + unit_pos(j, lane, r), a + j * U);
+            }
+            wave_sync();
+            if (sl / KR == r) {
+                const cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
+#pragma unroll
+                for (int j = 0; j < NU; ++j) {
+                    cx<T> t2[U];
+                    load_unit<T>(sp + j * U, t2);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[j * U + u] = widen<A>(t2[u]);
+                }
+            }
+        }
+    }
+
+    template <typename A>
+    __device__ static void store_from_segments(cx<T>* stg, const cx<A> (&v)[SZ], cx<T>* wp,
+                                               int lane) {
+        const int seg = lane % nseg, sl = lane / nseg;
+#pragma unroll
+        for (int r = 0; r < LPW / KR; ++r) {
+            wave_sync();
+            if (sl / KR == r) {
+                cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
+#pragma unroll
+                for (int j = 0; j < NU; ++j) {
+                    cx<T> t2[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) t2[u] = cx<T>{T(v[j * U + u].x), T(v[j * U + u].y)};
+                    store_unit<T>(sp + j * U, t2);
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int jj = 0; jj < JR; ++jj) {
+                const int j = r * JR + jj;
+                cx<T> t2[U];
+                load_unit<T>(stg + unit_pos(j, lane, r), t2);
+                store_unit<T>(wp + (j * 64 + lane) * U, t2);
+            }
+        }
+    }
+};
+
 // Small per-block tables (twiddles, Thomas factors) in registers: every load
 // issued first, staged in LDS after the block's other loads are in flight.
 template <typename V, int N, int NT>

@@ -73,7 +73,7 @@ template <typename T>
 hipError_t launch_r2c_density(const Plan& p, const void* psi, const double* sigma);
 template <typename T>
 hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin, const void* phin,
-                                double amp, double* partials);
+                                double amp, double* partials, int* nblocks);
 template <typename T>
 hipError_t launch_rows(const Plan& p, bool inverse);
 template <typename T>
@@ -124,6 +124,9 @@ template <typename T>
 bool fast_xmul(const Plan& p);
 template <typename T>
 bool fast_r2c(const Plan& p, const void* psi, const double* sigma);
+template <typename T>
+bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* phin, double amp,
+                  double* partials, int* nblocks);
 template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
 template <typename T>

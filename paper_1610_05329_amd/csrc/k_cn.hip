@@ -177,6 +177,63 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
     }
 }
 
+// Standalone z sweep, fast path (Nz = 64, 128 or 256, 16-point segments):
+// each wave owns LPW = 64 / nseg whole lines, loads them with coalesced
+// 16-byte units, transposes them through LDS to the segment layout, solves with
+// shuffle carries (the fused z pass's solver) and stores them back coalesced.
+// Waves are independent after the table staging: no block barrier follows it.
+template <typename T, int Nz, bool RC>
+__global__ void __launch_bounds__(256) k_cn_z2(cx<T>* __restrict__ f, int nlines,
+                                              const cx<double>* __restrict__ cntab,
+                                              cx<double> kappa64) {
+    using A = cn_acc_t<T, RC>;
+    constexpr int SZ = 16;
+    constexpr int NT = 256, NW = NT / 64;
+    constexpr int nseg = Nz / SZ;
+    constexpr int U = 16 / (int)sizeof(cx<T>);
+    constexpr int KR = (64 * U) / Nz > 1 ? (64 * U) / Nz : 1;
+    using WL = WaveLines<T, Nz, SZ, KR>;
+    constexpr int LPW = WL::LPW, NU = WL::NU;
+    constexpr int TS = Nz + Nz / SZ;
+    __shared__ __align__(16) cx<T> stg[NW * KR * WL::SL];
+    __shared__ cx<A> ta[TS];
+    __shared__ cx<A> tp[TS];
+    __shared__ cx<A> tq[TS];
+    __shared__ cx<A> spe[nseg];
+    __shared__ cx<A> sqb[nseg];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wl0 = (xcd_swizzle(blockIdx.x, gridDim.x) * NW + wv) * LPW;
+    TabRegs<cx<double>, Nz, NT> rta, rtp, rtq;
+    TabRegs<cx<double>, nseg, NT> rpe, rqb;
+    tab_issue(rta, cntab + TAB_ALPHA * Nz, tid);
+    tab_issue(rtp, cntab + TAB_P * Nz, tid);
+    tab_issue(rtq, cntab + TAB_Q * Nz, tid);
+    tab_issue(rpe, cntab + TAB_PEND * Nz, tid);
+    tab_issue(rqb, cntab + TAB_QBEG * Nz, tid);
+    // waves past the last line load the last wave's lines (unused)
+    cx<T>* wp = f + (size_t)min(wl0, nlines - LPW) * Nz;
+    cx<T> a[SZ];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) load_unit<T>(wp + (j * 64 + lane) * U, a + j * U);
+    const auto ident = [](int i) { return i; };
+    const auto padded = [](int i) { return i + i / SZ; };
+    tab_stage(rta, ta, tid, padded);
+    tab_stage(rtp, tp, tid, padded);
+    tab_stage(rtq, tq, tid, padded);
+    tab_stage(rpe, spe, tid, ident);
+    tab_stage(rqb, sqb, tid, ident);
+    __syncthreads();
+    if (wl0 >= nlines) return;  // no barrier follows
+    cx<T>* st = stg + wv * KR * WL::SL;
+    const int seg = lane % nseg;
+    cx<A> v[SZ];
+    WL::to_segments(st, a, v, lane);
+    const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
+    const int tb = seg * (SZ + 1);
+    cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
+    WL::store_from_segments(st, v, wp, lane);
+}
+
 }  // namespace
 
 cx_coef cn_kappa(const Plan& p, int axis, bool conjugate) {
@@ -227,7 +284,36 @@ hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
 }
 
 template <typename T>
+bool fast_cn_z(const Plan& p, void* f, bool conjugate) {
+    const int Nz = p.n[2];
+    const int nlines = p.n[0] * p.n[1];
+    const int lpw = 64 / (Nz / 16);
+    // the z tables hold 16-point segments when lc.seg[2] == 16
+    if (!p.fast || p.lc.seg[2] != 16 || (Nz != 64 && Nz != 128 && Nz != 256) || nlines % lpw)
+        return false;
+    const int blocks = (nlines / lpw + 3) / 4;
+    const cx<double>* tab = (const cx<double>*)p.cntab[2][conjugate ? 1 : 0];
+    const cx_coef k = cn_kappa(p, 2, conjugate);
+    const cx<double> kappa = {k.re, k.im};
+#define DGPE_CNZ2(NZ)                                                                           \
+    if (p.imag)                                                                                 \
+        hipLaunchKernelGGL((k_cn_z2<T, NZ, true>), dim3(blocks), dim3(256), 0, p.stream,        \
+                           (cx<T>*)f, nlines, tab, kappa);                                      \
+    else                                                                                        \
+        hipLaunchKernelGGL((k_cn_z2<T, NZ, false>), dim3(blocks), dim3(256), 0, p.stream,       \
+                           (cx<T>*)f, nlines, tab, kappa);
+    switch (Nz) {
+        case 64: DGPE_CNZ2(64) break;
+        case 128: DGPE_CNZ2(128) break;
+        default: DGPE_CNZ2(256) break;
+    }
+#undef DGPE_CNZ2
+    return true;
+}
+
+template <typename T>
 hipError_t launch_cn_z(const Plan& p, void* f, bool conjugate) {
+    if (fast_cn_z<T>(p, f, conjugate)) return hipGetLastError();
     const int Nz = p.n[2];
     const int logB = p.lc.logB_z;
     const int B = 1 << logB;

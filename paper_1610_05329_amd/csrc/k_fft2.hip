@@ -146,11 +146,24 @@ __device__ __forceinline__ cx<T> r2c_post2(cx<T> zk, cx<T> zm, cx<T> w) {
 // FFT of length M = Nz/2 = R1 R2, post-processing into the half spectrum,
 // kz-major store.  Lanes: t fastest.
 // ---------------------------------------------------------------------------
-template <typename T, int R1, int R2>
+// Physics of the pointwise steps (trap half-widths, spacings, trap_a^2 / 2)
+struct Phys2 {
+    double dt, g, gd, amp;
+    int imag;
+    int hx, hy, hz;
+    double dx, dy, dz, cx, cy, cz;
+};
+
+// ADJ: the transformed real field is the adjoint source
+// s = Im(conj(mu) e^{-i theta} psi_n), theta = dt (a V0 + g |psi_n|^2 + g_d Phi_n)
+// (psi holds mu), with the FP64 block sums of s V0, s x^2, s y^2, s z^2 in
+// partials[4 * block + q].
+template <typename T, int R1, int R2, bool ADJ>
 __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     k_r2c2(const cx<T>* __restrict__ psi, cx<T>* __restrict__ spec, int Nx, int Ny,
            const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
-           const double* __restrict__ sigma) {
+           const double* __restrict__ sigma, const cx<T>* __restrict__ psin,
+           const T* __restrict__ phin, Phys2 ph, double* __restrict__ partials) {
     constexpr int M = R1 * R2;
     constexpr int NB = rows_per_block<T, R1, M>();
     constexpr int NT = NB * R1;
@@ -174,18 +187,56 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     tab_issue(rr2, twr2c, tid);
     const cx<T>* base = psi + (line0 + b) * (2 * M);
     cx<T> pa[R2], pc[R2];
+    cx<T> qa[ADJ ? R2 : 1], qc[ADJ ? R2 : 1];
+    T fa[ADJ ? R2 : 1], fc[ADJ ? R2 : 1];
 #pragma unroll
     for (int n = 0; n < R2; ++n) {
         const int j = t + R1 * n;
         pa[n] = base[2 * j];
         pc[n] = base[2 * j + 1];
+        if constexpr (ADJ) {
+            const size_t o = (line0 + b) * (2 * M) + 2 * j;
+            qa[n] = psin[o];
+            qc[n] = psin[o + 1];
+            fa[n] = phin[o];
+            fc[n] = phin[o + 1];
+        }
     }
     tab_stage(rtw, stw, tid, [](int i) { return i; });
     tab_stage(rr2, sr2c, tid, [](int i) { return i; });
-    const T sig = sigma ? T(sigma[0]) : T(1);
     cx<T> v[R2];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (!ADJ) {
+        const T sig = sigma ? T(sigma[0]) : T(1);
 #pragma unroll
-    for (int n = 0; n < R2; ++n) v[n] = cx<T>{abs2(pa[n]) * sig, abs2(pc[n]) * sig};
+        for (int n = 0; n < R2; ++n) v[n] = cx<T>{abs2(pa[n]) * sig, abs2(pc[n]) * sig};
+    } else {
+        const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
+        const T xx = T(x - ph.hx) * T(ph.dx), yy = T(y0 + b - ph.hy) * T(ph.dy);
+        const T vxy = T(ph.cx) * xx * xx + T(ph.cy) * yy * yy;
+        const double x2 = double(x - ph.hx) * ph.dx * (double(x - ph.hx) * ph.dx);
+        const double y2 = double(y0 + b - ph.hy) * ph.dy * (double(y0 + b - ph.hy) * ph.dy);
+        auto source = [&](cx<T> m, cx<T> pn, T phi, int iz) {
+            const T z = T(iz - ph.hz) * T(ph.dz);
+            const T v0 = vxy + T(ph.cz) * z * z;
+            const T th = dt * (amp * v0 + gg * abs2(pn) + gdd * phi);
+            T sn, cs;
+            sin_cos(th, &sn, &cs);
+            const cx<T> pp = {pn.x * cs + pn.y * sn, pn.y * cs - pn.x * sn};
+            const T sv = m.x * pp.y - m.y * pp.x;  // Im(conj(m) pp)
+            const double zd = double(iz - ph.hz) * ph.dz;
+            acc[0] += double(sv) * double(v0);
+            acc[1] += double(sv) * x2;
+            acc[2] += double(sv) * y2;
+            acc[3] += double(sv) * zd * zd;
+            return sv;
+        };
+#pragma unroll
+        for (int n = 0; n < R2; ++n) {
+            const int j = t + R1 * n;
+            v[n] = cx<T>{source(pa[n], qa[n], fa[n], 2 * j), source(pc[n], qc[n], fc[n], 2 * j + 1)};
+        }
+    }
     __syncthreads();
     rdft<T, R2, false>(v);
     twiddle_phase<T, R2, false>(v, t, stw);
@@ -210,6 +261,14 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
         const cx<T> zk = xb[bl * SB + (k == M ? 0 : k)];
         const cx<T> zm = xb[bl * SB + (k == 0 ? 0 : M - k)];
         spec[(size_t)k * plane + line0 + bl] = r2c_post2(zk, zm, sr2c[k]);
+    }
+    if constexpr (ADJ) {
+        __shared__ double red[NT / 64];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double sum = block_sum(acc[q], red);
+            if (tid == 0) partials[(size_t)blockIdx.x * 4 + q] = sum;
+        }
     }
 }
 
@@ -341,12 +400,6 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 // LDS: region (xin / xb, then Phi pairs, then the z carries) | Psi tile |
 // twiddles | segment carry products.
 // ---------------------------------------------------------------------------
-struct Phys2 {
-    double dt, g, gd, amp;
-    int imag;
-    int hx, hy, hz;
-    double dx, dy, dz, cx, cy, cz;
-};
 
 // lines per block of the fused z pass: the state tile (Nz (NB+1) complex) must
 // fit next to the spectral region in 64 KB of LDS
@@ -370,47 +423,6 @@ constexpr int step2_threads() {
     constexpr int a = NB * R1, c = NB * nseg;
     constexpr int m = a > c ? a : c;
     return (m + 63) / 64 * 64;
-}
-
-// 16-byte units of the state: two FP32 or one FP64 complex values
-template <typename T>
-struct unit16;
-template <>
-struct unit16<float> {
-    using type = float4;
-};
-template <>
-struct unit16<double> {
-    using type = double2;
-};
-
-template <typename T>
-__device__ __forceinline__ void load_unit(const cx<T>* p, cx<T>* out) {
-    const auto q = *reinterpret_cast<const typename unit16<T>::type*>(p);
-    if constexpr (sizeof(T) == 4) {
-        out[0] = cx<T>{q.x, q.y};
-        out[1] = cx<T>{q.z, q.w};
-    } else {
-        out[0] = cx<T>{q.x, q.y};
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void store_unit(cx<T>* p, const cx<T>* in) {
-    typename unit16<T>::type q;
-    if constexpr (sizeof(T) == 4) {
-        q = float4{in[0].x, in[0].y, in[1].x, in[1].y};
-    } else {
-        q = double2{in[0].x, in[0].y};
-    }
-    *reinterpret_cast<typename unit16<T>::type*>(p) = q;
-}
-
-// Orders the LDS accesses of one wave (no cross-wave synchronisation)
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Staging geometry of the fused z pass.  A wave owns LPW = 64 / nseg whole
@@ -565,60 +577,16 @@ __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
     }
     // to the segment layout, KR lines per round, through this wave's Phi rows
     cx<T>* stg = reg + wv * LPW * PS;
-    const int seg = lane % nseg, sl = lane / nseg;
+    const int seg = lane % nseg;
     cx<A> v[SZ];
-#pragma unroll
-    for (int r = 0; r < LPW / KR; ++r) {
-        wave_sync();  // previous reads of the rows done
-#pragma unroll
-        for (int jj = 0; jj < JR; ++jj) {
-            const int j = r * JR + jj;
-            const int c = (j * 64 + lane) * U - r * KR * Nz;
-            const int e = c % Nz;
-            store_unit<T>(stg + (c / Nz) * SL + e + (e / SZ) * U, a + j * U);
-        }
-        wave_sync();
-        if (sl / KR == r) {
-            const cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
-#pragma unroll
-            for (int j = 0; j < NU; ++j) {
-                cx<T> t2[U];
-                load_unit<T>(sp + j * U, t2);
-#pragma unroll
-                for (int u = 0; u < U; ++u) v[j * U + u] = widen<A>(t2[u]);
-            }
-        }
-    }
+    WaveLines<T, Nz, SZ, KR>::to_segments(stg, a, v, lane);
     // Crank-Nicolson along z: the nseg segments of a line are nseg consecutive
     // lanes of one wave (carries by shuffles)
     const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
     const int tb = seg * (SZ + 1);
     cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
     // back to the load layout and out
-#pragma unroll
-    for (int r = 0; r < LPW / KR; ++r) {
-        wave_sync();
-        if (sl / KR == r) {
-            cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
-#pragma unroll
-            for (int j = 0; j < NU; ++j) {
-                cx<T> t2[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) t2[u] = to_store<T>(v[j * U + u]);
-                store_unit<T>(sp + j * U, t2);
-            }
-        }
-        wave_sync();
-#pragma unroll
-        for (int jj = 0; jj < JR; ++jj) {
-            const int j = r * JR + jj;
-            const int c = (j * 64 + lane) * U - r * KR * Nz;
-            const int e = c % Nz;
-            cx<T> t2[U];
-            load_unit<T>(stg + (c / Nz) * SL + e + (e / SZ) * U, t2);
-            store_unit<T>(wp + (j * 64 + lane) * U, t2);
-        }
-    }
+    WaveLines<T, Nz, SZ, KR>::store_from_segments(stg, v, wp, lane);
 }
 
 }  // namespace
@@ -694,9 +662,38 @@ bool fast_r2c(const Plan& p, const void* psi, const double* sigma) {
     switch (M) {
 #define DGPE_CASE(A, B)                                                                              \
     case A * B:                                                                                      \
-        hipLaunchKernelGGL((k_r2c2<T, A, B>), dim3(blocks), dim3(nb * A), 0, p.stream,              \
+        hipLaunchKernelGGL((k_r2c2<T, A, B, false>), dim3(blocks), dim3(nb * A), 0, p.stream,       \
                            (const cx<T>*)psi, (cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2], \
-                           (const cx<T>*)p.twr2c, sigma);                                            \
+                           (const cx<T>*)p.twr2c, sigma, (const cx<T>*)nullptr, (const T*)nullptr,  \
+                           Phys2{}, (double*)nullptr);                                               \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
+bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* phin, double amp,
+                  double* partials, int* nblocks) {
+    const int M = p.n[2] / 2;
+    const Split2 s = fast_split(M);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(M);
+    if (p.n[1] % nb) return false;
+    const int blocks = p.n[0] * (p.n[1] / nb);
+    if ((size_t)blocks * 4 > p.red_count) return false;
+    *nblocks = blocks;
+    Phys2 ph{p.dt, p.g, p.gd, amp, 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
+             p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
+             0.5 * p.trap[2] * p.trap[2]};
+    switch (M) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        hipLaunchKernelGGL((k_r2c2<T, A, B, true>), dim3(blocks), dim3(nb * A), 0, p.stream,        \
+                           (const cx<T>*)mu, (cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],  \
+                           (const cx<T>*)p.twr2c, (const double*)nullptr, (const cx<T>*)psin,       \
+                           (const T*)phin, ph, partials);                                            \
         return true;
         DGPE_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
@@ -770,6 +767,8 @@ bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
     template bool fast_rows<T>(const Plan&, bool);                   \
     template bool fast_xmul<T>(const Plan&);                         \
     template bool fast_r2c<T>(const Plan&, const void*, const double*); \
+    template bool fast_r2c_adj<T>(const Plan&, const void*, const void*, const void*, double, \
+                                  double*, int*);                   \
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
     template bool fast_c2r_step<T>(const Plan&, void*, const double*, double);
 DGPE_INST(float)

@@ -543,7 +543,9 @@ hipError_t launch_r2c_density(const Plan& p, const void* psi, const double* sigm
 
 template <typename T>
 hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin, const void* phin,
-                                double amp, double* partials) {
+                                double amp, double* partials, int* nblocks) {
+    if (p.fast && fast_r2c_adj<T>(p, mu, psin, phin, amp, partials, nblocks)) return hipGetLastError();
+    *nblocks = r2c_blocks(p);
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_r2c(p, es, sizeof(cx<T>));
     Phys ph{p.dt, p.g, p.gd, amp, 0};
@@ -645,7 +647,7 @@ hipError_t launch_ukern(const Plan& p) {
 #define DGPE_INST(T)                                                                               \
     template hipError_t launch_r2c_density<T>(const Plan&, const void*, const double*);            \
     template hipError_t launch_r2c_adjoint_s<T>(const Plan&, const void*, const void*, const void*, \
-                                                double, double*);                                  \
+                                                double, double*, int*);                            \
     template hipError_t launch_rows<T>(const Plan&, bool);                                         \
     template hipError_t launch_xmul<T>(const Plan&);                                               \
     template hipError_t launch_c2r_step<T>(const Plan&, void*, const double*, double);             \

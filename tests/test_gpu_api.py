@@ -93,6 +93,29 @@ def test_overlap_adjoint_matches_oracle(env, prec):
     assert _rel(out["dJ_dpsi0"].cpu().numpy().astype(np.complex128), lam0) < tol
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [((8, 32, 64), (0.45, 0.3, 0.2)), ((6, 32, 128), (0.5, 0.3, 0.1))],
+                         ids=lambda s: "x".join(map(str, s[0])))
+def test_adjoint_with_compiled_z_passes_matches_oracle(env, shape, prec):
+    """z lines of 64 and 128 points and 32 y lines take the compiled z passes
+    of the adjoint (the adjoint-source R2C and the conjugate z sweep with
+    coalesced loads and shuffle carries); energy objective against the oracle."""
+    torch, dg = env
+    n, d = shape
+    p = O.Params(n, d, 0.004, (1.0, 1.3, 1.1), 12.0, 7.0, False)
+    psi0 = W.random_state(n, d, seed=81)
+    amp = np.random.default_rng(82).uniform(0.8, 1.2, size=7)
+    J, psiN, dJ_da, dJ_dt, lam0 = O.adjoint_evolve(p, psi0, amp, "energy", None)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    plan = dg.Plan(n, d, p.dt, p.trap, p.g, p.gd, real_time=True, dtype=dt)
+    out = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=3)
+    tol = 1e-10 if prec == "f64" else 5e-4
+    assert abs(out["J"] - J) < tol * abs(J)
+    assert np.max(np.abs(out["dJ_damp"] - dJ_da)) < tol * np.max(np.abs(dJ_da))
+    assert np.max(np.abs(out["dJ_dtrap"] - dJ_dt)) < tol * np.max(np.abs(dJ_dt))
+    assert _rel(out["dJ_dpsi0"].cpu().numpy().astype(np.complex128), lam0) < tol
+
+
 def test_adjoint_independent_of_checkpoint_interval(env):
     torch, dg = env
     n, d = (16, 16, 24), (0.45, 0.45, 0.35)
