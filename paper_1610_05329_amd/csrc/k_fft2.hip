@@ -256,11 +256,21 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     }
     __syncthreads();
     const size_t plane = (size_t)Nx * Ny;
-    for (int g = tid; g < (M + 1) * NB; g += NT) {
-        const int k = g / NB, bl = g - k * NB;
-        const cx<T> zk = xb[bl * SB + (k == M ? 0 : k)];
-        const cx<T> zm = xb[bl * SB + (k == 0 ? 0 : M - k)];
-        spec[(size_t)k * plane + line0 + bl] = r2c_post2(zk, zm, sr2c[k]);
+    // two adjacent lines per thread and row: 16-byte stores in FP32
+    constexpr int P = sizeof(T) == 4 ? 2 : 1;
+    constexpr int NPB = NB / P;
+    static_assert(NB % P == 0, "pairs of lines");
+    for (int g = tid; g < (M + 1) * NPB; g += NT) {
+        const int k = g / NPB, bl = (g - k * NPB) * P;
+        cx<T> o[P];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const cx<T> zk = xb[(bl + q) * SB + (k == M ? 0 : k)];
+            const cx<T> zm = xb[(bl + q) * SB + (k == 0 ? 0 : M - k)];
+            o[q] = r2c_post2(zk, zm, sr2c[k]);
+        }
+        if constexpr (P == 2) store_unit<T>(spec + (size_t)k * plane + line0 + bl, o);
+        else spec[(size_t)k * plane + line0 + bl] = o[0];
     }
     if constexpr (ADJ) {
         __shared__ double red[NT / 64];
@@ -273,37 +283,44 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 }
 
 // Spectrum values of the z inverse transform for NB lines, in registers: the
-// (M+1) x NB block of X_k (k <= M) read in NSP rounds of NT threads, every load
-// issued before any is waited for.  Out-of-range slots of the last round read
-// the block's last value (in bounds) and are not staged.
+// (M+1) x NB block of X_k (k <= M) read in N rounds of NT threads, every load
+// issued before any is waited for; in FP32 each thread reads two adjacent lines
+// (16-byte loads).  Out-of-range slots of the last round read the block's last
+// unit (in bounds) and stage it again (see tab_stage).
 template <typename T, int M, int NB, int NT>
 struct SpecRegs {
-    static constexpr int N = ((M + 1) * NB + NT - 1) / NT;
-    cx<T> v[N];
+    static constexpr int P = sizeof(T) == 4 ? 2 : 1;  // lines per load
+    static constexpr int total = (M + 1) * (NB / P);  // loads per block
+    static constexpr int N = (total + NT - 1) / NT;
+    static_assert(NB % P == 0, "pairs of lines");
+    cx<T> v[N][P];
 };
 
 template <typename T, int M, int NB, int NT>
 __device__ __forceinline__ void c2r_issue_loads(SpecRegs<T, M, NB, NT>& r,
                                                 const cx<T>* __restrict__ spec, size_t plane,
                                                 size_t line0, int tid) {
-    constexpr int total = (M + 1) * NB;
+    using R = SpecRegs<T, M, NB, NT>;
 #pragma unroll
-    for (int u = 0; u < SpecRegs<T, M, NB, NT>::N; ++u) {
-        const int g = min(tid + u * NT, total - 1);
-        const int k = g / NB, bl = g - k * NB;
-        r.v[u] = spec[(size_t)k * plane + line0 + bl];
+    for (int u = 0; u < R::N; ++u) {
+        const int g = min(tid + u * NT, R::total - 1);
+        const int k = g / (NB / R::P), bl = (g - k * (NB / R::P)) * R::P;
+        const cx<T>* src = spec + (size_t)k * plane + line0 + bl;
+        if constexpr (R::P == 2) load_unit<T>(src, r.v[u]);
+        else r.v[u][0] = src[0];
     }
 }
 
 template <typename T, int M, int NB, int NT>
 __device__ __forceinline__ void c2r_stage(const SpecRegs<T, M, NB, NT>& r, cx<T>* xin, int tid) {
-    constexpr int total = (M + 1) * NB;
+    using R = SpecRegs<T, M, NB, NT>;
     constexpr int SI = M + 1;
 #pragma unroll
-    for (int u = 0; u < SpecRegs<T, M, NB, NT>::N; ++u) {
-        const int g = min(tid + u * NT, total - 1);  // see tab_stage
-        const int k = g / NB, bl = g - k * NB;
-        xin[bl * SI + k] = r.v[u];
+    for (int u = 0; u < R::N; ++u) {
+        const int g = min(tid + u * NT, R::total - 1);
+        const int k = g / (NB / R::P), bl = (g - k * (NB / R::P)) * R::P;
+#pragma unroll
+        for (int q = 0; q < R::P; ++q) xin[(bl + q) * SI + k] = r.v[u][q];
     }
 }
 
@@ -457,6 +474,7 @@ struct Step2Geom {
 // | twiddles.
 template <typename T, int R1, int R2, int SZ, bool RC>
 __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
+__attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     k_c2r_step2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
                 const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
