@@ -555,45 +555,38 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
         if constexpr (kPre) return al[kPre ? i : 0];
         else return widen<A>(ta[tb + i]);
     };
-    // 1. r'_i = u_{i-1} + u_{i+1} + kappa u_i
-    cx<A> prev = left;
+    // 1. forward recurrence from a zero carry, with r'_i = u_{i-1} + u_{i+1} +
+    // kappa u_i formed on the fly from the input values (threads without a
+    // segment read no table)
+    if (act) {
+        cx<A> dcur = {A(0), A(0)};
+        cx<A> prev = left, cur = widen<A>(v[0]);
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-        if (!GUARD || i < cnt) {
-            const cx<A> cur = widen<A>(v[i]);
+        for (int i = 0; i < S; ++i) {
             cx<A> nxt = right;
             if (i + 1 < S) {
                 if (!GUARD || i + 1 < cnt) nxt = widen<A>(v[(i + 1 < S) ? i + 1 : i]);
             }
-            v[i] = to_store<VS>(prev + nxt + kmul<RC>(kappa, cur));
-            prev = cur;
-        }
-    }
-    // 2. forward recurrence, zero carry (threads without a segment read no table)
-    if (act) {
-        cx<A> dcur = {A(0), A(0)};
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
             if (!GUARD || i < cnt) {
-                dcur = kmul<RC>(alpha(i), dcur + widen<A>(v[i]));
+                dcur = kmul<RC>(alpha(i), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
                 v[i] = to_store<VS>(dcur);
             }
+            prev = cur;
+            cur = nxt;
         }
         dl[seg * nlines + line] = dcur;
     }
     __syncthreads();
     if (act) {
-        // 3. true d before the segment's first point, from the segments on the left
-        cx<A> c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
-#pragma unroll
-        for (int i = 0; i < S; ++i)
-            if (!GUARD || i < cnt) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c));
-        // 4. back substitution, zero carry
+        // 2. true d before the segment's first point, from the segments on the
+        // left (P correction), then back substitution from a zero carry
+        const cx<A> c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
         cx<A> xcur = {A(0), A(0)};
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
             if (!GUARD || i < cnt) {
-                xcur = widen<A>(v[i]) + kmul<RC>(alpha(i), xcur);
+                const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
+                xcur = d + kmul<RC>(alpha(i), xcur);
                 v[i] = to_store<VS>(xcur);
             }
         }
@@ -634,21 +627,19 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
     cx<A> right = widen<A>(shfl_down_c(v[0], 1, NSEG));
     if (seg == 0) left = zero;
     if (seg == NSEG - 1) right = zero;
-    // r'_i = u_{i-1} + u_{i+1} + kappa u_i
-    cx<A> prev = left;
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-        const cx<A> cur = widen<A>(v[i]);
-        const cx<A> nxt = (i + 1 < S) ? widen<A>(v[(i + 1 < S) ? i + 1 : i]) : right;
-        v[i] = to_store<VS>(prev + nxt + kmul<RC>(kappa, cur));
-        prev = cur;
-    }
-    // forward recurrence from a zero carry
+    // forward recurrence from a zero carry, r'_i = u_{i-1} + u_{i+1} + kappa u_i
+    // formed on the fly from the input values
     cx<A> dcur = zero;
+    {
+        cx<A> prev = left, cur = widen<A>(v[0]);
 #pragma unroll
-    for (int i = 0; i < S; ++i) {
-        dcur = kmul<RC>(widen<A>(ta[i]), dcur + widen<A>(v[i]));
-        v[i] = to_store<VS>(dcur);
+        for (int i = 0; i < S; ++i) {
+            const cx<A> nxt = (i + 1 < S) ? widen<A>(v[(i + 1 < S) ? i + 1 : i]) : right;
+            dcur = kmul<RC>(widen<A>(ta[i]), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
+            v[i] = to_store<VS>(dcur);
+            prev = cur;
+            cur = nxt;
+        }
     }
     // inclusive scan over the segments of the line: d_end(s)
     cx<A> a = widen<A>(pend[seg]), b = dcur;
@@ -662,15 +653,14 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
     }
     cx<A> c = shfl_up_c(b, 1, NSEG);
     if (seg == 0) c = zero;
-#pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c));
-    // back substitution from a zero carry.  FP64 factors are read again here
-    // rather than kept live since the forward pass (64 registers)
+    // P correction and back substitution from a zero carry.  FP64 factors are
+    // read again here rather than kept live since the forward pass (64 registers)
     if constexpr (sizeof(A) == 8) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     cx<A> xcur = zero;
 #pragma unroll
     for (int i = S - 1; i >= 0; --i) {
-        xcur = widen<A>(v[i]) + kmul<RC>(widen<A>(ta[i]), xcur);
+        const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c);
+        xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
         v[i] = to_store<VS>(xcur);
     }
     // scan from the right: true x at the start of each segment
