@@ -155,7 +155,8 @@ size_t dgpe_adjoint_workspace_bytes(dgpe_plan plan, int32_t nsteps, int32_t ckpt
  *             DGPE_OBJ_OVERLAP: J = |sum conj(target) psi_N dV|^2 (target:
  *             device state of the plan precision).
  *   adj_ws    device buffer of >= dgpe_adjoint_workspace_bytes(); holds the
- *             checkpoints (every ckpt_every steps, recomputed per segment).
+ *             checkpoints (every ckpt_every steps), one segment of recomputed
+ *             states and the dipolar potential of each of them.
  * Outputs (host unless stated): J; dJ_damp[nsteps+1]; dJ_dtrap[3] for
  * (nu, lambda, gamma); psi_final (device, nullable) = psi_N; dJ_dpsi0 (device,
  * nullable) = the cotangent lam_0 with dJ = Re sum conj(lam_0) dpsi0.

@@ -310,8 +310,11 @@ struct PassTimer {
         DGPE_HIP((timer).end());        \
     } while (0)
 
+// nsteps steps in place on psi; with psi_in, the first step reads psi_in
+// instead (out of place) and, with phi_out, also writes Phi of psi_in's density.
 template <typename T>
-dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTimer* tm = nullptr) {
+dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTimer* tm = nullptr,
+                      const void* psi_in = nullptr, void* phi_out = nullptr) {
     PassTimer none;
     PassTimer& t = tm ? *tm : none;
     double* sigma = p.scal;
@@ -319,11 +322,12 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
     for (int s = 0; s < nsteps; ++s) {
         const double a = amp ? amp[s] : 1.0;
         const double* sg = (p.imag && s > 0) ? sigma : nullptr;
-        DGPE_PASS(t, 0, (launch_r2c_density<T>(p, psi, sg)));
+        const void* src = (s == 0 && psi_in) ? psi_in : psi;
+        DGPE_PASS(t, 0, (launch_r2c_density<T>(p, src, sg)));
         DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
         DGPE_PASS(t, 2, (launch_xmul<T>(p)));
         DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
-        DGPE_PASS(t, 4, (launch_c2r_step<T>(p, psi, sg, a)));
+        DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, s == 0 ? phi_out : nullptr)));
         DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
         DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr)));
         if (p.imag) DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb_x, sigma)));
@@ -403,8 +407,8 @@ AdjLayout adj_layout(const Plan& p, int nsteps, int K) {
     o += st * (size_t)K;
     L.lam = o;
     o += st;
-    L.phin = o;
-    o += align_up(nt * rsz);
+    L.phin = o;  // Phi of the segment's states, one slot per step
+    o += align_up(nt * rsz) * (size_t)K;
     L.phis = o;
     o += align_up(nt * rsz);
     L.sums = o;
@@ -426,7 +430,8 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
     const size_t st = align_up(nt * sizeof(T) * 2);
     auto state = [&](size_t base, int i) { return (void*)(ws + base + st * (size_t)i); };
     void* lam = ws + L.lam;
-    void* phin = ws + L.phin;
+    const size_t phi_bytes = align_up(nt * sizeof(T));
+    auto phi_slot = [&](int i) { return (void*)(ws + L.phin + phi_bytes * (size_t)i); };
     void* phis = ws + L.phis;
     double* sums = (double*)(ws + L.sums);
     double* part = (double*)(ws + L.part);
@@ -472,17 +477,22 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
     for (int s = L.nckpt - 1; s >= 0; --s) {
         const int n0 = s * K, len = std::min(K, nsteps - n0);
         DGPE_HIP(launch_copy<T>(p, state(L.seg, 0), state(L.ckpt, s)));
+        // recompute the segment out of place; each step also leaves Phi of
+        // the state it started from
         for (int i = 1; i < len; ++i) {
-            DGPE_HIP(launch_copy<T>(p, state(L.seg, i), state(L.seg, i - 1)));
-            dgpe_status stt = run_steps<T>(p, state(L.seg, i), 1, amp + n0 + i - 1);
+            dgpe_status stt = run_steps<T>(p, state(L.seg, i), 1, amp + n0 + i - 1, nullptr,
+                                           state(L.seg, i - 1), phi_slot(i - 1));
             if (stt != DGPE_OK) return stt;
         }
         for (int i = len - 1; i >= 0; --i) {
             const int n = n0 + i;
             void* psin = state(L.seg, i);
-            dgpe_status stt = convolve_density<T>(p, psin, nullptr);
-            if (stt != DGPE_OK) return stt;
-            DGPE_HIP(launch_c2r_phi<T>(p, phin));
+            void* phin = phi_slot(i);
+            if (i == len - 1) {  // the last state of the segment was never stepped from
+                dgpe_status stt = convolve_density<T>(p, psin, nullptr);
+                if (stt != DGPE_OK) return stt;
+                DGPE_HIP(launch_c2r_phi<T>(p, phin));
+            }
             DGPE_HIP(launch_cn_z<T>(p, lam, true));
             DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
             DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));

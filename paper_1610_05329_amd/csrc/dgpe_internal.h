@@ -79,7 +79,10 @@ hipError_t launch_rows(const Plan& p, bool inverse);
 template <typename T>
 hipError_t launch_xmul(const Plan& p);
 template <typename T>
-hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double amp);
+// P5 from psi_in to psi_out (may be the same buffer); phi_out (optional)
+// receives Phi of psi_in's density
+hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
+                           double amp, void* phi_out = nullptr);
 template <typename T>
 hipError_t launch_c2r_phi(const Plan& p, void* phi_out);
 template <typename T>
@@ -130,7 +133,8 @@ bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* p
 template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
 template <typename T>
-bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp);
+bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
+                   double amp, void* phi_out);
 
 // kappa = 1/A - 2 of the scaled Crank-Nicolson right-hand side (conj(A) for the adjoint)
 struct cx_coef {

@@ -472,10 +472,11 @@ struct Step2Geom {
 // (neighbours and carries by wave shuffles), and back for coalesced stores.
 // LDS: region (xin / xb, then Phi pairs, then the staging) | alpha, P, Q tables
 // | twiddles.
-template <typename T, int R1, int R2, int SZ, bool RC>
+template <typename T, int R1, int R2, int SZ, bool RC, bool PHI>
 __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
 __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
-    k_c2r_step2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
+    k_c2r_step2(const cx<T>* psi_in, cx<T>* psi_out, T* __restrict__ phi_out,
+                const cx<T>* __restrict__ spec, int Nx, int Ny,
                 const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
                 const double* __restrict__ sigma, Phys2 ph) {
@@ -529,10 +530,10 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     // the wave's LPW lines are LPW * Nz consecutive values; unit j of this lane
     // holds values (j * 64 + lane) * U + u (waves without lines load the last
     // wave's, unused, to keep the load sequence uniform)
-    cx<T>* wp = psi + (line0 + (size_t)min(wv * LPW, NB - LPW)) * Nz;
+    const size_t wl = (line0 + (size_t)min(wv * LPW, NB - LPW)) * Nz;  // the wave's first value
     cx<T> a[SZ];
 #pragma unroll
-    for (int j = 0; j < NU; ++j) load_unit<T>(wp + (j * 64 + lane) * U, a + j * U);
+    for (int j = 0; j < NU; ++j) load_unit<T>(psi_in + wl + (j * 64 + lane) * U, a + j * U);
     const auto ident = [](int i) { return i; };
     const auto padded = [](int i) { return i + i / SZ; };
     tab_stage(rtw, stw, tid, ident);
@@ -574,6 +575,10 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
         const T vxy = vx + T(ph.cy) * yy * yy;
         const int m = e0 >> 1;
         const cx<T> fv = prow[lw * PS + m + (m >> 3)];
+        if constexpr (PHI) {  // Phi of the pre-step density, for the adjoint
+            if constexpr (U == 2) *reinterpret_cast<cx<T>*>(phi_out + wl + c0) = fv;
+            else phi_out[wl + c0] = (e0 & 1) ? fv.y : fv.x;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = e0 + u;
@@ -604,7 +609,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     const int tb = seg * (SZ + 1);
     cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
     // back to the load layout and out
-    WaveLines<T, Nz, SZ, KR>::store_from_segments(stg, v, wp, lane);
+    WaveLines<T, Nz, SZ, KR>::store_from_segments(stg, v, psi_out + wl, lane);
 }
 
 }  // namespace
@@ -744,7 +749,8 @@ bool fast_c2r_phi(const Plan& p, void* phi) {
 #define DGPE_STEP_SPLITS(X) X(8, 4) X(8, 8) X(16, 8)
 
 template <typename T>
-bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
+bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
+                   double amp, void* phi_out) {
     const int M = p.n[2] / 2;
     if (p.lc.seg[2] != 16 || p.n[2] % 16) return false;
     int nb = 0;
@@ -764,15 +770,21 @@ bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
     const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
     const int blocks = p.n[0] * (p.n[1] / nb);
     switch (M) {
-#define DGPE_LAUNCH(A, B, RCV)                                                                      \
-    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV>), dim3(blocks),                              \
-                       dim3(step2_threads<T, A, B, 16>()), 0, p.stream, (cx<T>*)psi,                \
+#define DGPE_LAUNCH(A, B, RCV, PHIV)                                                                \
+    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV, PHIV>), dim3(blocks),                        \
+                       dim3(step2_threads<T, A, B, 16>()), 0, p.stream, (const cx<T>*)psi_in,       \
+                       (cx<T>*)psi_out, (T*)phi_out,                                                \
                        (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],                \
                        (const cx<T>*)p.twr2c, tab, kappa, sigma, ph)
-#define DGPE_CASE(A, B)                     \
-    case A * B:                             \
-        if (p.imag) DGPE_LAUNCH(A, B, true); \
-        else DGPE_LAUNCH(A, B, false);      \
+#define DGPE_CASE(A, B)                                  \
+    case A * B:                                          \
+        if (p.imag) {                                    \
+            if (phi_out) DGPE_LAUNCH(A, B, true, true);  \
+            else DGPE_LAUNCH(A, B, true, false);         \
+        } else {                                         \
+            if (phi_out) DGPE_LAUNCH(A, B, false, true); \
+            else DGPE_LAUNCH(A, B, false, false);        \
+        }                                                \
         return true;
         DGPE_STEP_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
@@ -788,7 +800,7 @@ bool fast_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
     template bool fast_r2c_adj<T>(const Plan&, const void*, const void*, const void*, double, \
                                   double*, int*);                   \
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
-    template bool fast_c2r_step<T>(const Plan&, void*, const double*, double);
+    template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*);
 DGPE_INST(float)
 DGPE_INST(double)
 #undef DGPE_INST

@@ -336,7 +336,8 @@ __device__ __forceinline__ void c2r_front(cx<T>* buf, cx<T>* stw, cx<T>* sr2c,
 // P5: z inverse transform -> Phi, nonlinear phase, Crank-Nicolson along z.
 // LDS: F (M+1 rows) | Psi (Nz rows) | twiddles | segment carry products.
 template <typename T, int SZ, bool RC, bool GUARD>
-__global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
+__global__ void __launch_bounds__(256) k_c2r_step(const cx<T>* psi_in, cx<T>* psi_out,
+                                                 T* __restrict__ phi_out,
                                                  const cx<T>* __restrict__ spec, int Nx, int Ny,
                                                  int Nz, int logB, int ES, FftDesc fz,
                                                  const cx<T>* __restrict__ twz,
@@ -373,14 +374,15 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
     const double sg = sigma ? sigma[0] : 1.0;
     const T sig = T(sg), rs = T(sqrt(sg));
     const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
-    cx<T>* base = psi + line0 * Nz;
+    const cx<T>* base_in = psi_in + line0 * Nz;
+    cx<T>* base = psi_out + line0 * Nz;
     const int total = B * Nz;
     for (int g0 = tid; g0 < total; g0 += kLU * nthr) {
         cx<T> a[kLU];
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
             const int g = g0 + u * nthr;
-            if (g < total) a[u] = base[g];
+            if (g < total) a[u] = base_in[g];
         }
 #pragma unroll
         for (int u = 0; u < kLU; ++u) {
@@ -389,6 +391,7 @@ __global__ void __launch_bounds__(256) k_c2r_step(cx<T>* __restrict__ psi,
                 const int b = g / Nz, e = g - b * Nz;
                 const cx<T> fv = F[(e >> 1) * ES + b];
                 const T phi = (e & 1) ? fv.y : fv.x;
+                if (phi_out) phi_out[line0 * Nz + g] = phi;  // for the adjoint
                 const T n = abs2(a[u]) * sig;
                 const T th = dt * (amp * trap_v0<T>(geo, x, y0 + b, e) + gg * n + gdd * phi);
                 cx<T> r;
@@ -590,8 +593,9 @@ hipError_t launch_xmul(const Plan& p) {
 }
 
 template <typename T>
-hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double amp) {
-    if (p.fast && fast_c2r_step<T>(p, psi, sigma, amp)) return hipGetLastError();
+hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
+                           double amp, void* phi_out) {
+    if (p.fast && fast_c2r_step<T>(p, psi_in, psi_out, sigma, amp, phi_out)) return hipGetLastError();
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
@@ -602,7 +606,8 @@ hipError_t launch_c2r_step(const Plan& p, void* psi, const double* sigma, double
     const bool guard = (p.n[2] % S) != 0;
 #define DGPE_C2R_STEP(SZV, RCV, GV)                                                                \
     hipLaunchKernelGGL((k_c2r_step<T, SZV, RCV, GV>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm, \
-                       p.stream, (cx<T>*)psi, (const cx<T>*)p.spec, p.n[0], p.n[1], p.n[2],         \
+                       p.stream, (const cx<T>*)psi_in, (cx<T>*)psi_out, (T*)phi_out,                \
+                       (const cx<T>*)p.spec, p.n[0], p.n[1], p.n[2],                                \
                        p.lc.logB_z, es, p.fz, (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, tab,    \
                        kappa, sigma, make_geo(p), ph, c2r_fcap(p, es, sizeof(cx<T>)))
 #define DGPE_C2R_S(SZV)                              \
@@ -650,7 +655,8 @@ hipError_t launch_ukern(const Plan& p) {
                                                 double, double*, int*);                            \
     template hipError_t launch_rows<T>(const Plan&, bool);                                         \
     template hipError_t launch_xmul<T>(const Plan&);                                               \
-    template hipError_t launch_c2r_step<T>(const Plan&, void*, const double*, double);             \
+    template hipError_t launch_c2r_step<T>(const Plan&, const void*, void*, const double*, double, \
+                                           void*);             \
     template hipError_t launch_c2r_phi<T>(const Plan&, void*);                                     \
     template hipError_t launch_ukern<T>(const Plan&);
 DGPE_INST(float)
