@@ -413,8 +413,8 @@ AdjLayout adj_layout(const Plan& p, int nsteps, int K) {
     o += align_up(nt * rsz);
     L.sums = o;
     o += align_up((size_t)(nsteps + 1) * 4 * sizeof(double));
-    L.part = o;
-    o += align_up(red_count_for(p.n, p.lc) * sizeof(double));
+    L.part = o;  // partials: one set per step of a segment
+    o += align_up(red_count_for(p.n, p.lc) * sizeof(double)) * (size_t)K;
     L.scratch = o;
     o += align_up(16 * sizeof(double));
     L.end = o;
@@ -435,6 +435,8 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
     void* phis = ws + L.phis;
     double* sums = (double*)(ws + L.sums);
     double* part = (double*)(ws + L.part);
+    const size_t set_stride = align_up(red_count_for(p.n, p.lc) * sizeof(double)) / sizeof(double);
+    int nbs = 0;  // partial blocks of the adjoint source pass (the same for every step)
     double* scratch = (double*)(ws + L.scratch);
     // forward sweep, storing the state at the start of every segment
     void* cur = state(L.seg, 0);
@@ -496,15 +498,15 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
             DGPE_HIP(launch_cn_z<T>(p, lam, true));
             DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
             DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));
-            int nbs = 0;
-            DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part, &nbs));
-            DGPE_HIP(launch_reduce(p, part, nbs, 4, sums + (size_t)n * 4, nullptr));
+            DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part + set_stride * i, &nbs));
             DGPE_HIP(launch_rows<T>(p, false));
             DGPE_HIP(launch_xmul<T>(p));
             DGPE_HIP(launch_rows<T>(p, true));
             DGPE_HIP(launch_c2r_phi<T>(p, phis));
             DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
         }
+        // the segment's source sums, one reduction block per step
+        DGPE_HIP(launch_reduce(p, part, nbs, 4, sums + (size_t)n0 * 4, nullptr, len, set_stride));
     }
     if (dJ_dpsi0) DGPE_HIP(launch_copy<T>(p, dJ_dpsi0, lam));
     DGPE_HIP(hipMemcpyAsync(hs.data(), sums, (size_t)nsteps * 4 * sizeof(double),

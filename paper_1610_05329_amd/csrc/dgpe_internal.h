@@ -113,7 +113,7 @@ hipError_t launch_copy(const Plan& p, void* dst, const void* src);
 // Deterministic fixed-order reduction of partials[nblocks][width] into
 // out[width] (FP64, Neumaier-compensated); optional 1/(sum[0] dV) into sigma.
 hipError_t launch_reduce(const Plan& p, const double* partials, int nblocks, int width, double* out,
-                         double* sigma_out);
+                         double* sigma_out, int nsets = 1, size_t set_stride = 0);
 // sigma = 1 / (sum of norm partials * dV)
 hipError_t launch_norm_finalize(const Plan& p, const double* partials, int nblocks, double* sigma);
 

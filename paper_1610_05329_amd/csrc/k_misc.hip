@@ -101,11 +101,15 @@ __global__ void __launch_bounds__(kRedThreads)
 }
 
 // out[w] = sum_b partials[b][w]: each thread a strided Neumaier sum, then a
-// fixed tree; identical inputs give bitwise identical outputs.
+// fixed tree; identical inputs give bitwise identical outputs.  Block j reduces
+// the j-th set of partials (at partials + j * set_stride) into out + j * width.
 __global__ void __launch_bounds__(kRedThreads)
     k_reduce(const double* __restrict__ partials, int nblocks, int width, double* __restrict__ out,
-             double* __restrict__ sigma_out, double dV) {
+             double* __restrict__ sigma_out, double dV, size_t set_stride) {
     __shared__ double ss[kRedThreads];
+    partials += blockIdx.x * set_stride;
+    if (out) out += (size_t)blockIdx.x * width;
+    if (blockIdx.x > 0) sigma_out = nullptr;
     for (int w = 0; w < width; ++w) {
         double s = 0.0, c = 0.0;
         for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
@@ -257,9 +261,9 @@ hipError_t launch_observables(const Plan& p, const void* psi, const void* phi, d
 }
 
 hipError_t launch_reduce(const Plan& p, const double* partials, int nblocks, int width, double* out,
-                         double* sigma_out) {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, p.stream, partials, nblocks, width,
-                       out, sigma_out, p.d[0] * p.d[1] * p.d[2]);
+                         double* sigma_out, int nsets, size_t set_stride) {
+    hipLaunchKernelGGL(k_reduce, dim3(nsets), dim3(kRedThreads), 0, p.stream, partials, nblocks,
+                       width, out, sigma_out, p.d[0] * p.d[1] * p.d[2], set_stride);
     return hipGetLastError();
 }
 
