@@ -502,8 +502,11 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
             DGPE_HIP(launch_rows<T>(p, false));
             DGPE_HIP(launch_xmul<T>(p));
             DGPE_HIP(launch_rows<T>(p, true));
-            DGPE_HIP(launch_c2r_phi<T>(p, phis));
-            DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
+            if (!(p.fast && fast_c2r_adjupd<T>(p, lam, psin, phin, amp[n]))) {
+                DGPE_HIP(launch_c2r_phi<T>(p, phis));
+                DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
+            }
+            DGPE_HIP(hipGetLastError());
         }
         // the segment's source sums, one reduction block per step
         DGPE_HIP(launch_reduce(p, part, nbs, 4, sums + (size_t)n0 * 4, nullptr, len, set_stride));

@@ -130,6 +130,9 @@ bool fast_r2c(const Plan& p, const void* psi, const double* sigma);
 template <typename T>
 bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* phin, double amp,
                   double* partials, int* nblocks);
+// fused C2R of Phi_s + adjoint nonlinear update (false: no compiled split)
+template <typename T>
+bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp);
 template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
 template <typename T>

@@ -412,6 +412,101 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     }
 }
 
+// Adjoint of the nonlinear step fused with the C2R of Phi_s = Phi[s] (the
+// convolved adjoint source, in the spectrum buffer): with
+// theta = dt (a V0 + g |psi_n|^2 + g_d Phi_n), s = Im(conj(mu) e^{-i theta} psi_n)
+// and w = dt (g s + g_d Phi_s),  lam <- e^{+i theta} mu + 2 w psi_n  (lam holds
+// mu on entry).  Phi_s stays in LDS; the pointwise update runs over the
+// block's NB lines in coalesced 16-byte units.
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+    k_c2r_adjupd2(cx<T>* __restrict__ lam, const cx<T>* __restrict__ psin,
+                  const T* __restrict__ phin, const cx<T>* __restrict__ spec, int Nx, int Ny,
+                  const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c, Phys2 ph) {
+    constexpr int M = R1 * R2;
+    constexpr int Nz = 2 * M;
+    constexpr int NB = rows_per_block<T, R1, M>();
+    constexpr int NT = NB * R1;
+    constexpr int PS = M + M / 8 + 1;
+    constexpr int U = 16 / (int)sizeof(cx<T>);
+    constexpr int NU = NB * Nz / (NT * U);
+    static_assert(NU * NT * U == NB * Nz, "whole units");
+    constexpr int REG = c2r_region<R1, R2, NB>() > NB * PS ? c2r_region<R1, R2, NB>() : NB * PS;
+    __shared__ cx<T> reg[REG];
+    __shared__ cx<T> stw[M];
+    __shared__ cx<T> sr2c[M + 1];
+    const int tid = threadIdx.x;
+    const int ngy = Ny / NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x = bid / ngy;
+    const int y0 = (bid - x * ngy) * NB;
+    const size_t line0 = (size_t)x * Ny + y0;
+    TabRegs<cx<T>, M, NT> rtw;
+    TabRegs<cx<T>, M + 1, NT> rr2;
+    SpecRegs<T, M, NB, NT> rs;
+    tab_issue(rtw, twz, tid);
+    tab_issue(rr2, twr2c, tid);
+    c2r_issue_loads(rs, spec, (size_t)Nx * Ny, line0, tid);
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
+    tab_stage(rr2, sr2c, tid, [](int i) { return i; });
+    c2r_stage(rs, reg, tid);
+    __syncthreads();
+    cx<T> w[R1];
+    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, tid);
+    __syncthreads();  // reg is rewritten with the Phi_s pairs
+    {
+        const int t = tid % R1, b = tid / R1;
+        if (t < R2) {
+#pragma unroll
+            for (int k = 0; k < R1; ++k) {
+                const int m = t + R2 * k;
+                reg[b * PS + m + (m >> 3)] = w[k];
+            }
+        }
+    }
+    __syncthreads();
+    const size_t base = line0 * Nz;
+    const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
+    const T xx = T(x - ph.hx) * T(ph.dx);
+    const T vx = T(ph.cx) * xx * xx;
+    cx<T> mu[NU * U], pn[NU * U];
+    T fn[NU * U];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int e = (i * NT + tid) * U;
+        load_unit<T>(lam + base + e, mu + i * U);
+        load_unit<T>(psin + base + e, pn + i * U);
+#pragma unroll
+        for (int u = 0; u < U; ++u) fn[i * U + u] = phin[base + e + u];
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int e = (i * NT + tid) * U;
+        const int b = e / Nz;
+        const T yy = T(y0 + b - ph.hy) * T(ph.dy);
+        const T vxy = vx + T(ph.cy) * yy * yy;
+        cx<T> o[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int iz = e % Nz + u;
+            const int mm = iz >> 1;
+            const cx<T> fs = reg[b * PS + mm + (mm >> 3)];
+            const T phis = (iz & 1) ? fs.y : fs.x;
+            const T z = T(iz - ph.hz) * T(ph.dz);
+            const T v0 = vxy + T(ph.cz) * z * z;
+            const cx<T> p = pn[i * U + u], m = mu[i * U + u];
+            const T th = dt * (amp * v0 + gg * abs2(p) + gdd * fn[i * U + u]);
+            T sn, cs;
+            sin_cos(th, &sn, &cs);
+            const cx<T> pp = {p.x * cs + p.y * sn, p.y * cs - p.x * sn};
+            const T sv = m.x * pp.y - m.y * pp.x;
+            const T wv = dt * (gg * sv + gdd * phis);
+            o[u] = cx<T>{m.x * cs - m.y * sn + T(2) * wv * p.x, m.y * cs + m.x * sn + T(2) * wv * p.y};
+        }
+        store_unit<T>(lam + base + e, o);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P5: z inverse transform -> Phi, nonlinear phase, Crank-Nicolson along z.
 // LDS: region (xin / xb, then Phi pairs, then the z carries) | Psi tile |
@@ -725,6 +820,30 @@ bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* p
 }
 
 template <typename T>
+bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp) {
+    const int M = p.n[2] / 2;
+    const Split2 s = fast_split(M);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(M);
+    if (p.n[1] % nb) return false;
+    const int blocks = p.n[0] * (p.n[1] / nb);
+    Phys2 ph{p.dt, p.g, p.gd, amp, 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
+             p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
+             0.5 * p.trap[2] * p.trap[2]};
+    switch (M) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        hipLaunchKernelGGL((k_c2r_adjupd2<T, A, B>), dim3(blocks), dim3(nb * A), 0, p.stream,        \
+                           (cx<T>*)lam, (const cx<T>*)psin, (const T*)phin, (const cx<T>*)p.spec,    \
+                           p.n[0], p.n[1], (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, ph);        \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
+template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi) {
     const int M = p.n[2] / 2;
     const Split2 s = fast_split(M);
@@ -800,6 +919,7 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
     template bool fast_r2c_adj<T>(const Plan&, const void*, const void*, const void*, double, \
                                   double*, int*);                   \
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
+    template bool fast_c2r_adjupd<T>(const Plan&, void*, const void*, const void*, double); \
     template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*);
 DGPE_INST(float)
 DGPE_INST(double)
