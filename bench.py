@@ -25,6 +25,7 @@ Other modes:
 import argparse
 import glob
 import hashlib
+import re
 import json
 import os
 import sys
@@ -210,11 +211,13 @@ def main():
     per_step_bytes = sum(pbytes.values())
     share = {k: v for k, v in ms.items() if v > 0}
     dom = max(share, key=share.get)  # longest average launch
+    kernel_of = dict(KERNEL_OF_PASS, cn_y="k_cn_ycarry") if plan.fused_y else KERNEL_OF_PASS
     ach = pbytes[dom] / (ms[dom] * 1e-3) / 1e9
     roofline = {
-        "bound": "hbm", "kernel": KERNEL_OF_PASS[dom], "pass": dom, "achieved": round(ach, 1),
+        "bound": "hbm", "kernel": kernel_of[dom], "pass": dom, "fused_y": plan.fused_y,
+        "achieved": round(ach, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-        "traffic": traffic_for(KERNEL_OF_PASS[dom], 1),
+        "traffic": traffic_for(kernel_of[dom], 1),
         "avg_launch_ms": round(ms[dom], 5), "algorithmic_bytes_per_launch": pbytes[dom],
         "per_pass_ms": {k: round(v, 5) for k, v in ms.items()},
         "per_pass_GBs": {k: round(pbytes[k] / (ms[k] * 1e-3) / 1e9, 1) for k in share},
@@ -289,13 +292,10 @@ def main():
 # ---------------------------------------------------------------------------
 
 def _short(name):
-    for k in ("k_r2c2", "k_rows2", "k_xmul2", "k_c2r_step2", "k_c2r_phi2", "k_r2c_z", "k_rows",
-              "k_xmul", "k_c2r_step", "k_c2r_phi", "k_cn_strided", "k_cn_z", "k_reduce", "k_scale",
-              "k_observables", "k_ukern"):
-        if k in name:
-            tmpl = name[name.find(k):]
-            return tmpl.split("(")[0]
-    return name.split("(")[0][:60]
+    """Kernel name with its template arguments, without return type, namespaces
+    and parameter list (this library's kernels are all named k_*)."""
+    m = re.search(r"\b(k_\w+(?:<[^()]*>)?)\(", name)
+    return m.group(1) if m else name.split("(")[0][:60]
 
 
 def _counter_means(d):

@@ -81,6 +81,9 @@ typedef enum {
 #define DGPE_PARAM_DT 5
 #define DGPE_PARAM_REAL_TIME 6 /* value 1: real time, 0: imaginary time */
 #define DGPE_PARAM_FAST_FFT 7  /* 1 (default): compiled two-factor FFT passes where available; 0: generic passes only */
+#define DGPE_PARAM_FUSED_Y 8   /* 1 (default): in imaginary time, the fused z pass also solves the y axis in
+                                  16-line segments and pass 5 joins them (see the pass list); 0: the
+                                  separate y sweep.  Same result to rounding either way */
 
 /* adjoint objectives */
 #define DGPE_OBJ_ENERGY 0
@@ -125,6 +128,11 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value);
 
 /* Redirect subsequent work to another HIP stream. */
 dgpe_status dgpe_plan_set_stream(dgpe_plan plan, void* hip_stream);
+
+/* 1 if dgpe_step on this plan, as it is now set, runs the fused y schedule
+ * (DGPE_PARAM_FUSED_Y and the conditions in the pass list below), 0 if it
+ * runs the separate y sweep, -1 for a NULL plan.  Host only. */
+int32_t dgpe_plan_fused_y(dgpe_plan plan);
 
 /* Advance psi (device, [Nx][Ny][Nz] complex of the plan precision, in place) by
  * nsteps split steps.  amp: host array of nsteps trap amplitudes a(t_n) (NULL:
@@ -171,7 +179,11 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
  *   2 FFT along x, U_R multiply, inverse FFT along x
  *   3 inverse FFT along y        4 C2R along z + nonlinear phase + CN along z
  *   5 CN along y                 6 CN along x (+ norm partials, imaginary time)
- *   7 norm reduction (imaginary time) */
+ *   7 norm reduction (imaginary time)
+ * With DGPE_PARAM_FUSED_Y in effect (imaginary time, compiled fused pass,
+ * Ny a multiple of 16 up to 256): pass 4 also solves y in 16-line segments
+ * with zero carries, pass 5 is the segment carry pass, and pass 6 adds the
+ * carries before the x solve. */
 #define DGPE_NPASS 8
 
 /* Algorithmic HBM bytes of one launch of each pass for this plan: every array

@@ -97,8 +97,15 @@ class Plan:
             return torch.zeros(self.n, dtype=self.dtype, device=self.device)
         return torch.from_numpy(np.ascontiguousarray(array)).to(self.dtype).to(self.device).contiguous()
 
+    @property
+    def fused_y(self):
+        """True when step() runs the fused y schedule (the z pass starts the y
+        solve in 16-line segments, a carry pass joins them)."""
+        return self.lib.dgpe_plan_fused_y(self.handle) == 1
+
     def set(self, name, value):
-        """Change one parameter: g, gd, nu, lambda, gamma, dt or real_time."""
+        """Change one parameter: g, gd, nu, lambda, gamma, dt, real_time,
+        fast_fft (0/1) or fused_y (0/1)."""
         check(self.lib.dgpe_plan_set(self.handle, _lib.PARAM[name], float(value)))
         if name == "g":
             self.g = float(value)

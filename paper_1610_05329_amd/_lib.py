@@ -24,7 +24,8 @@ STATUS_NAMES = {
     4: "DGPE_EHIP", 5: "DGPE_ENONFINITE", 6: "DGPE_ESTATE",
 }
 DGPE_IMAG, DGPE_REAL, DGPE_F64, DGPE_F32 = 0, 1, 0, 2
-PARAM = {"g": 0, "gd": 1, "nu": 2, "lambda": 3, "gamma": 4, "dt": 5, "real_time": 6, "fast_fft": 7}
+PARAM = {"g": 0, "gd": 1, "nu": 2, "lambda": 3, "gamma": 4, "dt": 5, "real_time": 6, "fast_fft": 7,
+         "fused_y": 8}
 OBJECTIVE = {"energy": 0, "overlap": 1}
 NPASS = 8
 PASS_NAMES = ["r2c_z", "fft_y", "fft_x_mul", "ifft_y", "c2r_z_nonlinear_cn_z", "cn_y", "cn_x", "norm_reduce"]
@@ -45,6 +46,7 @@ SIGNATURES = {
                                    c_void_p]),
     "dgpe_plan_set": (c_int32, [c_void_p, c_int32, c_double]),
     "dgpe_plan_set_stream": (c_int32, [c_void_p, c_void_p]),
+    "dgpe_plan_fused_y": (c_int32, [c_void_p]),
     "dgpe_step": (c_int32, [c_void_p, c_void_p, c_int32, P_double]),
     "dgpe_potential": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "dgpe_energy_mu_rms": (c_int32, [c_void_p, c_void_p, c_double, ctypes.POINTER(DgpeObs)]),

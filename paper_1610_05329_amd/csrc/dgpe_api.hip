@@ -194,7 +194,7 @@ std::vector<T> twiddles(int L, int count) {
 template <typename T>
 std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
     using C = std::complex<long double>;
-    std::vector<C> al(N), P(N), Q(N), pend(N, C(0)), qbeg(N, C(0));
+    std::vector<C> al(N), P(N), Q(N), E(N), pend(N, C(0)), qbeg(N, C(0));
     const C diag = C(1) + C(2) * A;
     C m = C(1) / diag;
     for (int i = 0; i < N; ++i) {
@@ -209,6 +209,8 @@ std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
         acc = 1;
         for (int i = s1 - 1; i >= s0; --i) { acc *= al[i]; Q[i] = acc; }
         qbeg[k] = acc;
+        acc = 0;
+        for (int i = s1 - 1; i >= s0; --i) { acc = P[i] + al[i] * acc; E[i] = acc; }
     }
     std::vector<T> out(2 * TAB_COUNT * (size_t)N);
     const std::vector<C>* tabs[TAB_COUNT];
@@ -217,6 +219,7 @@ std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
     tabs[TAB_Q] = &Q;
     tabs[TAB_PEND] = &pend;
     tabs[TAB_QBEG] = &qbeg;
+    tabs[TAB_E] = &E;
     for (int t = 0; t < TAB_COUNT; ++t)
         for (int i = 0; i < N; ++i) {
             out[2 * ((size_t)t * N + i)] = (T)(*tabs[t])[i].real();
@@ -310,6 +313,24 @@ struct PassTimer {
         DGPE_HIP((timer).end());        \
     } while (0)
 
+// The y solve starts inside the fused z pass (16-line segments, zero carries),
+// a carry pass joins the segments and the x sweep adds the carries while it
+// loads: FP32 imaginary time, compiled fused pass, Ny / 16 <= 16 segments,
+// state under 4 GiB (32-bit offsets in the x sweep).  The carry inputs
+// ([3][Nx][Ny/16][Nz] complex) and the carry pairs (the same count times 2),
+// together 5/16 of the state's bytes, live in the Phi buffer (half the
+// state's bytes), which stepping does not otherwise use in imaginary time.
+template <typename T>
+bool use_fused_y(const Plan& p) {
+    const size_t state = (size_t)p.n[0] * p.n[1] * p.n[2] * 2 * sizeof(T);
+    // FP32 only: the FP64 x sweep with the carries added runs at two waves
+    // per SIMD and loses more than the y sweep it replaces
+    return sizeof(T) == 4 && p.fuse_y && p.fast && p.imag && p.n[1] / 16 <= 16 &&
+           state < (size_t(1) << 32) && fast_c2r_step_yfused_ok<T>(p);
+}
+
+bool fused_y(const Plan& p) { return p.f32 ? use_fused_y<float>(p) : use_fused_y<double>(p); }
+
 // nsteps steps in place on psi; with psi_in, the first step reads psi_in
 // instead (out of place) and, with phi_out, also writes Phi of psi_in's density.
 template <typename T>
@@ -318,18 +339,28 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
     PassTimer none;
     PassTimer& t = tm ? *tm : none;
     double* sigma = p.scal;
-    const int nb_x = cn_strided_blocks(p, 0);
+    void* car = use_fused_y<T>(p) ? p.phi : nullptr;
+    const size_t car_bytes = (size_t)p.n[0] * (p.n[1] / 16) * p.n[2] * 2 * sizeof(T);  // one array
+    const int nb_x = cn_strided_blocks(p, 0, car != nullptr);
     for (int s = 0; s < nsteps; ++s) {
         const double a = amp ? amp[s] : 1.0;
         const double* sg = (p.imag && s > 0) ? sigma : nullptr;
         const void* src = (s == 0 && psi_in) ? psi_in : psi;
+        void* phs = s == 0 ? phi_out : nullptr;
         DGPE_PASS(t, 0, (launch_r2c_density<T>(p, src, sg)));
         DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
         DGPE_PASS(t, 2, (launch_xmul<T>(p)));
         DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
-        DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, s == 0 ? phi_out : nullptr)));
-        DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
-        DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr)));
+        if (car && !phs) {
+            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, nullptr, car)));
+            DGPE_PASS(t, 5, (launch_cn_ycarry<T>(p, car)));
+            DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.red,
+                                                  (char*)car + 3 * car_bytes)));
+        } else {
+            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, phs)));
+            DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
+            DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr)));
+        }
         if (p.imag) DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb_x, sigma)));
     }
     if (p.imag && nsteps > 0) DGPE_HIP(launch_scale<T>(p, psi, sigma));
@@ -349,7 +380,13 @@ void pass_bytes(const Plan& p, double b[DGPE_NPASS]) {
     b[4] = spec + 2.0 * state;   // read S and psi, write psi
     b[5] = 2.0 * state;          // psi in place
     b[6] = 2.0 * state;
-    b[7] = p.imag ? 8.0 * cn_strided_blocks(p, 0) + 8.0 : 0.0;
+    if (fused_y(p)) {
+        const double car = state / 16.0;  // one carry array [Nx][Ny/16][Nz]
+        b[4] += 3.0 * car;                // + the three carry inputs
+        b[5] = 5.0 * car;                 // carry pass: read 3, write the (c_d, c_x) pairs
+        b[6] += 2.0 * car;                // x sweep: + c_d, c_x
+    }
+    b[7] = p.imag ? 8.0 * cn_strided_blocks(p, 0, fused_y(p)) + 8.0 : 0.0;
 }
 
 template <typename T>
@@ -628,6 +665,7 @@ dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[
     p->fy = factor(n[1]);
     p->fz = factor(n[2] / 2);
     p->fast = true;
+    p->fuse_y = true;
     st = f32 ? build_tables<float>(*p) : build_tables<double>(*p);
     if (st != DGPE_OK) {
         delete p;
@@ -650,6 +688,10 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
         case DGPE_PARAM_FAST_FFT:
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "FAST_FFT takes 0 or 1");
             p.fast = value == 1.0;
+            return DGPE_OK;
+        case DGPE_PARAM_FUSED_Y:
+            if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "FUSED_Y takes 0 or 1");
+            p.fuse_y = value == 1.0;
             return DGPE_OK;
         case DGPE_PARAM_DT:
             if (!(value > 0)) return fail(DGPE_EINVAL, "dt must be > 0");
@@ -674,6 +716,11 @@ dgpe_status dgpe_plan_set_stream(dgpe_plan plan, void* hip_stream) {
     if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
     plan->stream = (hipStream_t)hip_stream;
     return DGPE_OK;
+}
+
+int32_t dgpe_plan_fused_y(dgpe_plan plan) {
+    if (!plan) return -1;
+    return fused_y(*plan) ? 1 : 0;
 }
 
 dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp) {

@@ -459,6 +459,53 @@ struct WaveLines {
     }
 };
 
+// Raw buffer access (vector memory instructions): a resource over `bytes`
+// bytes from `base`, a per-lane 32-bit byte offset and a wave-uniform byte
+// offset, so a lane keeps one address register however many strided values it
+// moves.  Reads past the range return zero and writes past it are dropped.
+// Third descriptor word: the gfx9 raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> buf_load_cx(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    typedef unsigned v2u __attribute__((ext_vector_type(2)));
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    if constexpr (sizeof(T) == 4) {
+        const v2u q = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+        return __builtin_bit_cast(cx<T>, q);
+    } else {
+        const v4u q = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+        return __builtin_bit_cast(cx<T>, q);
+    }
+}
+
+// Two FP32 complex values in one 16-byte access.  The loaded vector is
+// reinterpreted whole: extracting its elements one by one after the builtin
+// compiled to a single dword load replicated into all four.
+template <typename T>
+struct cx2 {
+    cx<T> a, b;
+};
+
+template <typename T>
+__device__ __forceinline__ cx2<T> buf_load_cx2(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+    static_assert(sizeof(T) == 4, "16-byte pair of FP32 complex values");
+    typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    const v4u q = __builtin_amdgcn_raw_buffer_load_b128(r, vo, so, 0);
+    return __builtin_bit_cast(cx2<T>, q);
+}
+
+template <typename T>
+__device__ __forceinline__ void buf_store_cx(cx<T> v, __amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                             uint32_t so) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r, vo, so, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) unsigned, v), r, vo, so, 0);
+}
+
 // Small per-block tables (twiddles, Thomas factors) in registers: every load
 // issued first, staged in LDS after the block's other loads are in flight.
 template <typename V, int N, int NT>

@@ -26,8 +26,10 @@ struct FastDiv {
 // stored back to back, for (1 - A D) x = (1 + A D) u with zero ghosts:
 //   alpha_i = A m_i with Thomas pivots m_0 = 1/(1 + 2A), m_i = 1/(1 + 2A - A^2 m_{i-1})
 //   P_i = prod_{j = seg start}^{i} alpha_j,  Q_i = prod_{j = i}^{seg end - 1} alpha_j
-//   PEND[k] = P at the last point of segment k, QBEG[k] = Q at its first point.
-enum { TAB_ALPHA = 0, TAB_P = 1, TAB_Q = 2, TAB_PEND = 3, TAB_QBEG = 4, TAB_COUNT = 5 };
+//   PEND[k] = P at the last point of segment k, QBEG[k] = Q at its first point,
+//   E_i = P_i + alpha_i E_{i+1} (E = 0 past the segment end): the response of
+//   the back substitution to a unit forward carry entering the segment.
+enum { TAB_ALPHA = 0, TAB_P = 1, TAB_Q = 2, TAB_PEND = 3, TAB_QBEG = 4, TAB_E = 5, TAB_COUNT = 6 };
 
 // Launch parameters of the seven passes for one plan (host side).
 struct Launch {
@@ -63,6 +65,7 @@ struct Plan {
     FftDesc fx, fy, fz;
     Launch lc;
     bool fast;  // use the two-factor register FFT passes where compiled
+    bool fuse_y;  // let the fused z pass start the y solve where it can
 };
 
 size_t workspace_layout(const int n[3], bool f32, size_t* offs /* [16] or null */);
@@ -80,15 +83,25 @@ template <typename T>
 hipError_t launch_xmul(const Plan& p);
 template <typename T>
 // P5 from psi_in to psi_out (may be the same buffer); phi_out (optional)
-// receives Phi of psi_in's density
+// receives Phi of psi_in's density; ycar (optional, imaginary time, the
+// compiled pass only): also solve the y axis in 16-line segments with zero
+// carries, writing the three carry inputs [3][Nx][Ny/16][Nz] there
 hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                           double amp, void* phi_out = nullptr);
+                           double amp, void* phi_out = nullptr, void* ycar = nullptr);
 template <typename T>
 hipError_t launch_c2r_phi(const Plan& p, void* phi_out);
 template <typename T>
 hipError_t launch_cn_z(const Plan& p, void* f, bool conjugate);
 template <typename T>
-hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate, double* norm_partials);
+// ycar (x axis, imaginary time): add the y segment carries c_d, c_x (the
+// pairs launch_cn_ycarry writes after the three input arrays) to the values
+// as they are loaded
+hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate, double* norm_partials,
+                             const void* ycar = nullptr);
+// (c_d, c_x) pairs of the y segments, tiled for the x sweep, at car + 3
+// arrays, from the three carry inputs written by the fused z pass
+template <typename T>
+hipError_t launch_cn_ycarry(const Plan& p, void* car);
 template <typename T>
 hipError_t launch_scale(const Plan& p, void* psi, const double* sigma);
 template <typename T>
@@ -117,7 +130,10 @@ hipError_t launch_reduce(const Plan& p, const double* partials, int nblocks, int
 // sigma = 1 / (sum of norm partials * dV)
 hipError_t launch_norm_finalize(const Plan& p, const double* partials, int nblocks, double* sigma);
 
-int cn_strided_blocks(const Plan& p, int axis);
+// columns per block (log2) and block count of the strided sweep; ycarry: the
+// variant that completes the y carries (at most 512 threads per block)
+int cn_strided_logzb(const Plan& p, int axis, bool ycarry = false);
+int cn_strided_blocks(const Plan& p, int axis, bool ycarry = false);
 
 // Two-factor register FFT passes (k_fft2.hip); false when the length has no
 // compiled fast path (the caller then uses the generic Stockham kernel).
@@ -137,7 +153,11 @@ template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
 template <typename T>
 bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                   double amp, void* phi_out);
+                   double amp, void* phi_out, void* ycar);
+// the compiled fused z pass can start the y solve for this plan (blocks of whole
+// 16-line y segments, imaginary time)
+template <typename T>
+bool fast_c2r_step_yfused_ok(const Plan& p);
 
 // kappa = 1/A - 2 of the scaled Crank-Nicolson right-hand side (conj(A) for the adjoint)
 struct cx_coef {

@@ -33,13 +33,31 @@ CnTab tab_of(const void* base, int N) {
 template <typename A>
 __device__ __forceinline__ cx<A> narrow_tab(cx<double> v) { return cx<A>{A(v.x), A(v.y)}; }
 
+// A table entry; with real coefficients (imaginary time) the imaginary parts
+// are zero and only the real part is read.
+template <bool RC>
+__device__ __forceinline__ cx<double> tab_at(const cx<double>* t, int i) {
+    if constexpr (RC) return cx<double>{reinterpret_cast<const double*>(t)[2 * i], 0.0};
+    else return t[i];
+}
+
 // LDS: A1[nseg*ZB] | A2[nseg*ZB] (arithmetic type) | alpha | P | Q (each
 // nseg*(S+1): segment s at s*(S+1), so that the segments of a wave read
 // distinct banks) | pend | qbeg
-template <typename T, int S, bool RC, bool GUARD>
-__global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2 : kMaxThreads)
+//
+// YC (x axis only): the input is the local solution of the y solve split in
+// 16-line segments, and every value is completed first as
+// u += E_y c_d(x, y / 16, z) + Q_y c_x(x, y / 16, z), with the pairs
+// (c_d, c_x) from the carry pass at ycar, tiled per block
+// ([Ny/16][Nz/ZB][Nx][ZB][2]: the blocks of one segment and z range read one
+// contiguous tile), and E, Q from the y tables.
+template <typename T, int S, bool RC, bool GUARD, bool YC>
+__global__ void __launch_bounds__(YC || sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2 : kMaxThreads)
+__attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8)))
     k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab tg,
-                 cx<double> kappa64, double* __restrict__ norm_partials) {
+                 cx<double> kappa64, double* __restrict__ norm_partials,
+                 const cx<T>* __restrict__ ycar, const cx<double>* __restrict__ ytab, int Ny,
+                 int Nz) {
     using A = cn_acc_t<T, RC>;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double s_red[kMaxThreads / 64];
@@ -58,8 +76,8 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
     // clamped: the writes below are unconditional so the loads stay ahead of
     // the state loads; see tab_stage), then the state, then staging.
     const int i0 = min(tid, L - 1), s0 = min(tid, nseg - 1);
-    const cx<double> a0 = tg.a[i0], p0 = tg.p[i0], q0 = tg.q[i0];
-    const cx<double> pe0 = tg.pend[s0], qb0 = tg.qbeg[s0];
+    const cx<double> a0 = tab_at<RC>(tg.a, i0), p0 = tab_at<RC>(tg.p, i0), q0 = tab_at<RC>(tg.q, i0);
+    const cx<double> pe0 = tab_at<RC>(tg.pend, s0), qb0 = tab_at<RC>(tg.qbeg, s0);
     const cx<A> kappa = narrow_tab<A>(kappa64);
     const int ncb = C >> logZB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -70,10 +88,56 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
     const int e0 = seg * S;
     const int cnt = (seg < nseg) ? min(S, L - e0) : 0;
     cx<T>* base = f + (size_t)o * L * C + c0 + cl;
+    // YC: the column's y carry factors, then its carries after the state
+    const int ycol = YC ? (c0 + cl) / Nz : 0, zcol = YC ? (c0 + cl) - ycol * Nz : 0;
+    cx<double> ey64 = {0.0, 0.0}, qy64 = {0.0, 0.0};
+    if constexpr (YC) {
+        ey64 = tab_at<RC>(ytab, TAB_E * Ny + ycol);
+        qy64 = tab_at<RC>(ytab, TAB_Q * Ny + ycol);
+    }
+    // YC (x axis, state under 4 GiB): buffer accesses, one address register
+    // per lane for the state and one for the carry pairs
+    constexpr uint32_t csz = sizeof(cx<T>);
+    const uint32_t cstep = (uint32_t)C * csz;  // one x step of the state
+    const uint32_t foff = ((uint32_t)e0 * (uint32_t)C + (uint32_t)(c0 + cl)) * csz;
+    const __amdgpu_buffer_rsrc_t rf = buf_rsrc(f, YC ? (uint32_t)L * cstep : 0u);
     cx<A> v[S];
 #pragma unroll
     for (int i = 0; i < S; ++i)
-        if (!GUARD || i < cnt) v[i] = widen<A>(base[(size_t)(e0 + i) * C]);
+        if (!GUARD || i < cnt) {
+            if constexpr (YC)
+                v[i] = widen<A>(buf_load_cx<T>(rf, foff, i * cstep));
+            else
+                v[i] = widen<A>(base[(size_t)(e0 + i) * C]);
+        }
+    if constexpr (YC) {
+        const uint32_t kst = (uint32_t)ZB * 2 * csz;  // one x step of the pairs
+        const uint32_t tile = (uint32_t)(ycol >> 4) * (uint32_t)(Nz >> logZB) + (uint32_t)(zcol >> logZB);
+        const uint32_t coff = ((tile * (uint32_t)L + (uint32_t)e0) * (uint32_t)ZB + (uint32_t)cl) * 2 * csz;
+        const __amdgpu_buffer_rsrc_t rc =
+            buf_rsrc(ycar, (uint32_t)(Ny >> 4) * (uint32_t)(Nz >> logZB) * (uint32_t)L * kst);
+        cx<T> cc[S][2];
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (!GUARD || i < cnt) {
+                if constexpr (sizeof(T) == 4) {  // the pair is one 16-byte access
+                    const cx2<T> q = buf_load_cx2<T>(rc, coff, i * kst);
+                    cc[i][0] = q.a;
+                    cc[i][1] = q.b;
+                } else {
+                    cc[i][0] = buf_load_cx<T>(rc, coff, i * kst);
+                    cc[i][1] = buf_load_cx<T>(rc, coff + csz, i * kst);
+                }
+            }
+        // every load is issued: keep the table staging (which waits for the
+        // table loads) below this point
+        __builtin_amdgcn_sched_barrier(0);
+        const cx<A> ey = narrow_tab<A>(ey64), qy = narrow_tab<A>(qy64);
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+            if (!GUARD || i < cnt)
+                v[i] = v[i] + kmul<RC>(ey, widen<A>(cc[i][0])) + kmul<RC>(qy, widen<A>(cc[i][1]));
+    }
     ta[i0 + i0 / S] = narrow_tab<A>(a0);
     tp[i0 + i0 / S] = narrow_tab<A>(p0);
     tq[i0 + i0 / S] = narrow_tab<A>(q0);
@@ -113,7 +177,10 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
     for (int i = 0; i < S; ++i) {
         if (!GUARD || i < cnt) {
             const cx<T> o = to_store<T>(v[i]);
-            base[(size_t)(e0 + i) * C] = o;
+            if constexpr (YC)
+                buf_store_cx<T>(o, rf, foff, i * cstep);
+            else
+                base[(size_t)(e0 + i) * C] = o;
             acc += double(abs2(o));
         }
     }
@@ -121,6 +188,84 @@ __global__ void __launch_bounds__(sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2
         const double s = block_sum(acc, s_red);
         if (tid == 0) norm_partials[blockIdx.x] = s;
     }
+}
+
+// Carries of the y solve split in 16-line segments by the fused z pass.  One
+// thread per (x, z) column with K = Ny / 16 <= KM segments; arrays q of car
+// ([3][Nx][K][Nz]): 0 local d at the segment's last line plus u there (dl +
+// ul), 1 local x at its first line plus u there (xf + uf), 2 u at its first
+// line (uf).  With the Thomas factors alpha, the segment products PEND, QBEG
+// and the carry response E (y tables):
+//   forward:  c_d(0) = 0,  c_d(k+1) = (dl + ul)(k) + alpha_last(k) uf(k+1) + PEND(k) c_d(k)
+//             (the true d at the segment's last line, plus the next segment's
+//             left neighbour)
+//   backward: c_x(K-1) = 0,  c_x(k-1) = (xf + uf)(k) + E_first(k) c_d(k) + QBEG(k) c_x(k)
+//             (the true x at the segment's first line, plus the previous
+//             segment's right neighbour), uf(K) = 0.
+// The pairs (c_d(k), c_x(k)) go after the three arrays, tiled for the x
+// sweep: [K][Nz/ZB][Nx][ZB][2] with ZB = 2^lzb columns per sweep block.  Every
+// load of the column is issued before the first use.
+template <typename T, bool RC, int KM>
+__global__ void __launch_bounds__(64) k_cn_ycarry(cx<T>* __restrict__ car, int Nx, int Ny, int Nz,
+                                                 const cx<double>* __restrict__ ytab, int lzb) {
+    using A = cn_acc_t<T, RC>;
+    // per segment: alpha at its last line, PEND, E at its first line, QBEG
+    __shared__ cx<A> sf[4][KM];
+    const int K = Ny >> 4;
+    const int tid = threadIdx.x;
+    const int g = blockIdx.x * 64 + tid;
+    // table loads first (one per thread, clamped), then the column's values
+    const int tq = min(tid / KM, 3), tk = min(tid % KM, K - 1);
+    const int tix = tq == 0 ? TAB_ALPHA * Ny + 16 * tk + 15
+                  : tq == 1 ? TAB_PEND * Ny + tk
+                  : tq == 2 ? TAB_E * Ny + 16 * tk
+                            : TAB_QBEG * Ny + tk;
+    const cx<double> tv = tab_at<RC>(ytab, tix);
+    const bool act = g < Nx * Nz;
+    const int gg = act ? g : 0;
+    const int x = gg / Nz, z = gg - x * Nz;
+    const size_t cst = (size_t)Nx * K * Nz;
+    cx<T>* c0 = car + (size_t)x * K * Nz + z;
+    cx<T> dl[KM], xf[KM], uf[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < K) {
+            const size_t o = (size_t)k * Nz;
+            dl[k] = c0[o];
+            xf[k] = c0[cst + o];
+            uf[k] = c0[2 * cst + o];
+        }
+    if (tid < 4 * KM) sf[tq][tid % KM] = narrow_tab<A>(tv);
+    __syncthreads();
+    if (!act) return;
+    const cx<A> zero = {A(0), A(0)};
+    cx<A> cd[KM];
+    cx<A> c = zero;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (k < K) {
+            cd[k] = c;
+            const cx<A> ufn = k + 1 < K ? widen<A>(uf[k + 1 < KM ? k + 1 : k]) : zero;
+            c = widen<A>(dl[k]) + kmul<RC>(sf[0][k], ufn) + kmul<RC>(sf[1][k], c);
+        }
+    const int zbm = (1 << lzb) - 1;
+    const size_t ktile = (size_t)(Nz >> lzb) * Nx << lzb;  // pairs per segment
+    cx<T>* pr = car + 3 * cst +
+                ((((size_t)(z >> lzb) * Nx + x) << lzb) + (z & zbm)) * 2;
+    c = zero;
+#pragma unroll
+    for (int k = KM - 1; k >= 0; --k)
+        if (k < K) {
+            const cx<A> cxk = c;
+            c = widen<A>(xf[k]) + kmul<RC>(sf[2][k], cd[k]) + kmul<RC>(sf[3][k], cxk);
+            cx<T> t2[2] = {to_store<T>(cd[k]), to_store<T>(cxk)};
+            if constexpr (sizeof(T) == 4) {
+                store_unit<T>(pr + (size_t)k * ktile * 2, t2);
+            } else {
+                pr[(size_t)k * ktile * 2] = t2[0];
+                pr[(size_t)k * ktile * 2 + 1] = t2[1];
+            }
+        }
 }
 
 // Standalone z sweep of B = 2^logB contiguous lines, staged through LDS.
@@ -243,43 +388,82 @@ cx_coef cn_kappa(const Plan& p, int axis, bool conjugate) {
     return cx_coef{-2.0, conjugate ? 1.0 / a : -1.0 / a};
 }
 
-int cn_strided_blocks(const Plan& p, int axis) {
-    const int zb = 1 << p.lc.logZB[axis];
+int cn_strided_logzb(const Plan& p, int axis, bool ycarry) {
+    int logZB = p.lc.logZB[axis];
+    if (!ycarry) return logZB;
+    // the carry-completing variant holds two more values per point: blocks of
+    // at most kMaxThreads / 2 (fewer columns per block when the line needs it)
+    const int nseg = (p.n[axis] + p.lc.seg[axis] - 1) / p.lc.seg[axis];
+    while (logZB > 0 && (nseg << logZB) > kMaxThreads / 2) --logZB;
+    return (nseg << logZB) > kMaxThreads / 2 ? -1 : logZB;
+}
+
+int cn_strided_blocks(const Plan& p, int axis, bool ycarry) {
+    const int lz = cn_strided_logzb(p, axis, ycarry);
+    if (lz < 0) return 0;
+    const int zb = 1 << lz;
     if (axis == 1) return p.n[0] * (p.n[2] / zb);
     return (p.n[1] * p.n[2]) / zb;
 }
 
 template <typename T>
 hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
-                             double* norm_partials) {
+                             double* norm_partials, const void* ycar) {
+    if (ycar && (axis != 0 || conjugate || !p.imag || p.lc.seg[1] != 16 || p.n[1] % 16))
+        return hipErrorInvalidValue;
     const int L = p.n[axis];
     const int C = (axis == 1) ? p.n[2] : p.n[1] * p.n[2];
     const int S = p.lc.seg[axis];
-    const int logZB = p.lc.logZB[axis];
+    const int logZB = cn_strided_logzb(p, axis, ycar != nullptr);
     const int nseg = (L + S - 1) / S;
+    if (logZB < 0 || (ycar && (1 << logZB) > p.n[2])) return hipErrorInvalidValue;
     const int threads = nseg << logZB;
     const CnTab tg = tab_of(p.cntab[axis][conjugate ? 1 : 0], L);
     const cx_coef k = cn_kappa(p, axis, conjugate);
     const cx<double> kappa = {k.re, k.im};
-    const int blocks = cn_strided_blocks(p, axis);
+    const int blocks = cn_strided_blocks(p, axis, ycar != nullptr);
     const size_t asz = (p.imag ? sizeof(T) : sizeof(double)) * 2;
     const size_t sm = (size_t)(2 * threads + 3 * nseg * (S + 1) + 2 * nseg) * asz;
     const bool guard = (L % S) != 0;
-#define DGPE_CN(SV, RCV, GV)                                                                      \
-    hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV>), dim3(blocks), dim3(threads), sm, p.stream, \
-                       (cx<T>*)f, L, C, logZB, nseg, tg, kappa, norm_partials)
-#define DGPE_CN_S(SV)                           \
-    if (p.imag) {                               \
-        if (guard) DGPE_CN(SV, true, true);     \
-        else DGPE_CN(SV, true, false);          \
-    } else {                                    \
-        if (guard) DGPE_CN(SV, false, true);    \
-        else DGPE_CN(SV, false, false);         \
+    const cx<double>* ytab = (const cx<double>*)p.cntab[1][0];
+#define DGPE_CN(SV, RCV, GV, YV)                                                                      \
+    hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV, YV>), dim3(blocks), dim3(threads), sm, p.stream, \
+                       (cx<T>*)f, L, C, logZB, nseg, tg, kappa, norm_partials, (const cx<T>*)ycar,    \
+                       ytab, p.n[1], p.n[2])
+#define DGPE_CN_S(SV)                                  \
+    if (p.imag) {                                      \
+        if (ycar) {                                    \
+            if (guard) DGPE_CN(SV, true, true, true);  \
+            else DGPE_CN(SV, true, false, true);       \
+        } else if (guard) DGPE_CN(SV, true, true, false); \
+        else DGPE_CN(SV, true, false, false);          \
+    } else {                                           \
+        if (guard) DGPE_CN(SV, false, true, false);    \
+        else DGPE_CN(SV, false, false, false);         \
     }
     if (S == 16) { DGPE_CN_S(16) }
     else return hipErrorInvalidValue;
 #undef DGPE_CN_S
 #undef DGPE_CN
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cn_ycarry(const Plan& p, void* car) {
+    const int K = p.n[1] / 16;
+    if (!p.imag || p.lc.seg[1] != 16 || p.n[1] % 16 || K > 16) return hipErrorInvalidValue;
+    const int blocks = (p.n[0] * p.n[2] + 63) / 64;
+    const cx<double>* ytab = (const cx<double>*)p.cntab[1][0];
+    // the tiling of the pairs follows the x sweep that reads them
+    const int lzb = cn_strided_logzb(p, 0, true);
+    if (lzb < 0 || (1 << lzb) > p.n[2]) return hipErrorInvalidValue;
+#define DGPE_YC(KMV)                                                                           \
+    hipLaunchKernelGGL((k_cn_ycarry<T, true, KMV>), dim3(blocks), dim3(64), 0, p.stream,       \
+                       (cx<T>*)car, p.n[0], p.n[1], p.n[2], ytab, lzb)
+    if (K <= 4) DGPE_YC(4);
+    else if (K <= 8) DGPE_YC(8);
+    else DGPE_YC(16);
+#undef DGPE_YC
     return hipGetLastError();
 }
 
@@ -347,7 +531,8 @@ hipError_t launch_cn_z(const Plan& p, void* f, bool conjugate) {
 }
 
 #define DGPE_INST(T)                                                                  \
-    template hipError_t launch_cn_strided<T>(const Plan&, void*, int, bool, double*); \
+    template hipError_t launch_cn_strided<T>(const Plan&, void*, int, bool, double*, const void*); \
+    template hipError_t launch_cn_ycarry<T>(const Plan&, void*); \
     template hipError_t launch_cn_z<T>(const Plan&, void*, bool);
 DGPE_INST(float)
 DGPE_INST(double)

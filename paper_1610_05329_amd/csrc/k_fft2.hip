@@ -567,14 +567,29 @@ struct Step2Geom {
 // (neighbours and carries by wave shuffles), and back for coalesced stores.
 // LDS: region (xin / xb, then Phi pairs, then the staging) | alpha, P, Q tables
 // | twiddles.
-template <typename T, int R1, int R2, int SZ, bool RC, bool PHI>
+//
+// YF: the block's NB lines are NB / 16 whole segments of the y axis (16 lines
+// each), and the y Crank-Nicolson solve is started here: after the z solve the
+// lines are transposed through LDS (half of z at a time) and every (segment,
+// z) column is solved with zero carries and without its two outside
+// neighbours (u at the lines just before and after the segment).  By
+// linearity the exact solution is that local one plus E_i c_d + Q_i c_x, where
+// c_d is the true forward value entering the segment plus the left neighbour,
+// c_x the true solution after the segment plus the right neighbour.  The
+// block writes the local solution to psi_out and, per column, three arrays
+// [Nx][Ny/16][Nz] to ycar: d at the last line plus u there, x at the first
+// line plus u there, and u at the first line; the carry pass turns these into
+// c_d and c_x, which the x sweep adds while it loads.
+template <typename T, int R1, int R2, int SZ, bool RC, bool PHI, bool YF>
 __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
 __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     k_c2r_step2(const cx<T>* psi_in, cx<T>* psi_out, T* __restrict__ phi_out,
                 const cx<T>* __restrict__ spec, int Nx, int Ny,
                 const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
-                const double* __restrict__ sigma, Phys2 ph) {
+                const double* __restrict__ sigma, Phys2 ph,
+                const cx<double>* __restrict__ ytab, cx<double> kappay64,
+                cx<T>* __restrict__ ycar) {
     using A = cn_acc_t<T, RC>;
     using G = Step2Geom<T, R1, R2, SZ>;
     constexpr int M = G::M, Nz = G::Nz, nseg = G::nseg, LPW = G::LPW, U = G::U, NU = G::NU;
@@ -598,6 +613,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     __shared__ cx<A> sqb[nseg];
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
+    __shared__ cx<A> sya[YF ? NB : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const bool act = wv * LPW < NB;  // wave-uniform
@@ -621,6 +637,8 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     tab_issue(rtq, cntab + TAB_Q * Nz, tid);
     tab_issue(rpe, cntab + TAB_PEND * Nz, tid);
     tab_issue(rqb, cntab + TAB_QBEG * Nz, tid);
+    TabRegs<cx<double>, YF ? NB : 1, NT> rya;
+    if constexpr (YF) tab_issue(rya, ytab + TAB_ALPHA * Ny + y0, tid);
     c2r_issue_loads(rsp, spec, (size_t)Nx * Ny, line0, tid);
     // the wave's LPW lines are LPW * Nz consecutive values; unit j of this lane
     // holds values (j * 64 + lane) * U + u (waves without lines load the last
@@ -638,6 +656,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     tab_stage(rtq, tq, tid, padded);
     tab_stage(rpe, spe, tid, ident);
     tab_stage(rqb, sqb, tid, ident);
+    if constexpr (YF) tab_stage(rya, sya, tid, ident);
     c2r_stage(rsp, reg, tid);
     __syncthreads();
     cx<T> w[R1];
@@ -654,7 +673,10 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
         }
     }
     __syncthreads();
-    if (!act) return;  // no barrier follows
+    if (!YF && !act) return;  // no barrier follows (YF: the y phase has barriers)
+    const int seg = lane % nseg;
+    cx<A> v[SZ];
+    if (act) {
     // nonlinear step in the load layout (pre-step density, lazily normalised)
     const double sg = sigma ? sigma[0] : 1.0;
     const T sig = T(sg), rs = T(sqrt(sg));
@@ -695,8 +717,6 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     }
     // to the segment layout, KR lines per round, through this wave's Phi rows
     cx<T>* stg = reg + wv * LPW * PS;
-    const int seg = lane % nseg;
-    cx<A> v[SZ];
     WaveLines<T, Nz, SZ, KR>::to_segments(stg, a, v, lane);
     // Crank-Nicolson along z: the nseg segments of a line are nseg consecutive
     // lanes of one wave (carries by shuffles)
@@ -704,7 +724,69 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     const int tb = seg * (SZ + 1);
     cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
     // back to the load layout and out
-    WaveLines<T, Nz, SZ, KR>::store_from_segments(stg, v, psi_out + wl, lane);
+    if constexpr (!YF) WaveLines<T, Nz, SZ, KR>::store_from_segments(stg, v, psi_out + wl, lane);
+    }  // act
+    if constexpr (YF) {
+        // local y solve of 16-line segments, half of z per round: lines padded
+        // by one 16-byte unit per 16 values
+        constexpr int HZ = Nz / 2, LS = HZ + U * (HZ / 16), NSY = NB / 16;
+        static_assert(SZ == 16 && NB % 16 == 0 && NB * LS <= REG && HZ * NSY <= NT,
+                      "y segments of 16 lines, one half of z per round in the region");
+        const cx<A> zero = {A(0), A(0)};
+        const cx<A> kappay = {A(kappay64.x), A(kappay64.y)};
+        const int nky = Ny / 16;
+        const size_t cst = (size_t)Nx * nky * Nz;  // one carry array
+        const int col = tid % HZ, ys = tid / HZ;
+        const int sl = lane / nseg;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();  // staging reads (and the previous round's) done
+            const int z0 = seg * SZ - h * HZ;
+            if (act && z0 >= 0 && z0 < HZ) {
+                cx<T>* dst = reg + (wv * LPW + sl) * LS + z0 + U * (z0 / 16);
+#pragma unroll
+                for (int j = 0; j < SZ / U; ++j) {
+                    cx<T> t2[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) t2[u] = to_store<T>(v[j * U + u]);
+                    store_unit<T>(dst + j * U, t2);
+                }
+            }
+            __syncthreads();
+            if (tid < HZ * NSY) {
+                cx<A> w2[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    w2[j] = widen<A>(reg[(ys * 16 + j) * LS + col + U * (col / 16)]);
+                const cx<A>* al = sya + ys * 16;
+                const cx<A> ufirst = w2[0], ulast = w2[15];
+                cx<A> d = zero, prev = zero;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const cx<A> cur = w2[j];
+                    const cx<A> nxt = j < 15 ? w2[j < 15 ? j + 1 : j] : zero;
+                    d = kmul<RC>(al[j], d + (prev + nxt + kmul<RC>(kappay, cur)));
+                    prev = cur;
+                    w2[j] = d;
+                }
+                const cx<A> dlast = d;
+                cx<A> xv = zero;
+#pragma unroll
+                for (int j = 15; j >= 0; --j) {
+                    xv = w2[j] + kmul<RC>(al[j], xv);
+                    w2[j] = xv;
+                }
+                const int z = h * HZ + col;
+                cx<T>* out = psi_out + (line0 + ys * 16) * Nz + z;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) out[(size_t)j * Nz] = to_store<T>(w2[j]);
+                const size_t ci = ((size_t)x * nky + (y0 >> 4) + ys) * Nz + z;
+                ycar[ci] = to_store<T>(dlast + ulast);
+                ycar[cst + ci] = to_store<T>(w2[0] + ufirst);
+                ycar[2 * cst + ci] = to_store<T>(ufirst);
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -868,42 +950,60 @@ bool fast_c2r_phi(const Plan& p, void* phi) {
 #define DGPE_STEP_SPLITS(X) X(8, 4) X(8, 8) X(16, 8)
 
 template <typename T>
-bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                   double amp, void* phi_out) {
+int fast_c2r_step_lines(const Plan& p) {
     const int M = p.n[2] / 2;
-    if (p.lc.seg[2] != 16 || p.n[2] % 16) return false;
+    if (p.lc.seg[2] != 16 || p.n[2] % 16) return 0;
     int nb = 0;
     switch (M) {
 #define DGPE_CASE(A, B) \
     case A * B: nb = step2_nb<T, A, B, 16>(); break;
         DGPE_STEP_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
-        default: return false;
+        default: return 0;
     }
-    if (p.n[1] % nb) return false;
+    return p.n[1] % nb ? 0 : nb;
+}
+
+template <typename T>
+bool fast_c2r_step_yfused_ok(const Plan& p) {
+    const int nb = fast_c2r_step_lines<T>(p);
+    return nb > 0 && nb % 16 == 0 && p.imag && p.lc.seg[1] == 16 && p.n[1] % 16 == 0;
+}
+
+template <typename T>
+bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
+                   double amp, void* phi_out, void* ycar) {
+    const int M = p.n[2] / 2;
+    const int nb = fast_c2r_step_lines<T>(p);
+    if (!nb) return false;
+    if (ycar && (phi_out || !fast_c2r_step_yfused_ok<T>(p))) return false;
     const cx_coef k = cn_kappa(p, 2, false);
     const cx<double> kappa = {k.re, k.im};
+    const cx_coef ky = cn_kappa(p, 1, false);
+    const cx<double> kappay = {ky.re, ky.im};
     Phys2 ph{p.dt, p.g, p.gd, amp, p.imag ? 1 : 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
              p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
              0.5 * p.trap[2] * p.trap[2]};
     const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
+    const cx<double>* ytab = (const cx<double>*)p.cntab[1][0];
     const int blocks = p.n[0] * (p.n[1] / nb);
     switch (M) {
-#define DGPE_LAUNCH(A, B, RCV, PHIV)                                                                \
-    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV, PHIV>), dim3(blocks),                        \
+#define DGPE_LAUNCH(A, B, RCV, PHIV, YFV)                                                           \
+    hipLaunchKernelGGL((k_c2r_step2<T, A, B, 16, RCV, PHIV, YFV>), dim3(blocks),                   \
                        dim3(step2_threads<T, A, B, 16>()), 0, p.stream, (const cx<T>*)psi_in,       \
                        (cx<T>*)psi_out, (T*)phi_out,                                                \
                        (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],                \
-                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph)
-#define DGPE_CASE(A, B)                                  \
-    case A * B:                                          \
-        if (p.imag) {                                    \
-            if (phi_out) DGPE_LAUNCH(A, B, true, true);  \
-            else DGPE_LAUNCH(A, B, true, false);         \
-        } else {                                         \
-            if (phi_out) DGPE_LAUNCH(A, B, false, true); \
-            else DGPE_LAUNCH(A, B, false, false);        \
-        }                                                \
+                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph, ytab, kappay, (cx<T>*)ycar)
+#define DGPE_CASE(A, B)                                         \
+    case A * B:                                                 \
+        if (p.imag) {                                           \
+            if (ycar) DGPE_LAUNCH(A, B, true, false, true);     \
+            else if (phi_out) DGPE_LAUNCH(A, B, true, true, false); \
+            else DGPE_LAUNCH(A, B, true, false, false);         \
+        } else {                                                \
+            if (phi_out) DGPE_LAUNCH(A, B, false, true, false); \
+            else DGPE_LAUNCH(A, B, false, false, false);        \
+        }                                                       \
         return true;
         DGPE_STEP_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
@@ -920,7 +1020,9 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
                                   double*, int*);                   \
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
     template bool fast_c2r_adjupd<T>(const Plan&, void*, const void*, const void*, double); \
-    template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*);
+    template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*, \
+                                   void*);                                                        \
+    template bool fast_c2r_step_yfused_ok<T>(const Plan&);
 DGPE_INST(float)
 DGPE_INST(double)
 #undef DGPE_INST

@@ -594,8 +594,10 @@ hipError_t launch_xmul(const Plan& p) {
 
 template <typename T>
 hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                           double amp, void* phi_out) {
-    if (p.fast && fast_c2r_step<T>(p, psi_in, psi_out, sigma, amp, phi_out)) return hipGetLastError();
+                           double amp, void* phi_out, void* ycar) {
+    if (p.fast && fast_c2r_step<T>(p, psi_in, psi_out, sigma, amp, phi_out, ycar))
+        return hipGetLastError();
+    if (ycar) return hipErrorInvalidValue;  // only the compiled fused pass starts the y solve
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
@@ -656,7 +658,7 @@ hipError_t launch_ukern(const Plan& p) {
     template hipError_t launch_rows<T>(const Plan&, bool);                                         \
     template hipError_t launch_xmul<T>(const Plan&);                                               \
     template hipError_t launch_c2r_step<T>(const Plan&, const void*, void*, const double*, double, \
-                                           void*);             \
+                                           void*, void*);      \
     template hipError_t launch_c2r_phi<T>(const Plan&, void*);                                     \
     template hipError_t launch_ukern<T>(const Plan&);
 DGPE_INST(float)

@@ -239,3 +239,36 @@ def test_fast_and_generic_fft_paths_agree(dg, torch_mod, shape, real_time, prec)
     _say(f"  fast {e_fast:.2e} generic {e_gen:.2e} fast-vs-generic {e_ab:.2e}; phi {p_fast:.2e} {p_gen:.2e}")
     assert max(e_fast, e_gen, e_ab) < TOL[prec]
     assert max(p_fast, p_gen) < (1e-13 if prec == "f64" else 2e-6)
+
+
+FUSED_Y_SHAPES = [
+    ((16, 64, 256), (0.4, 0.3, 0.1)),    # 16 lines per z-pass block, 4 y segments
+    ((24, 96, 128), (0.35, 0.2, 0.2)),   # 32 lines per block (2 segments), 6 segments
+    ((24, 32, 64), (0.4, 0.4, 0.3)),     # 32 lines per block, half the block's waves idle
+    ((12, 256, 256), (0.5, 0.08, 0.1)),  # 16 segments, x lines shorter than a segment
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", FUSED_Y_SHAPES, ids=lambda s: "x".join(map(str, s[0])))
+def test_fused_y_schedule_matches_oracle(dg, torch_mod, shape, prec):
+    """FP32 imaginary time with the y solve started in the fused z pass
+    (16-line segments, zero carries), joined by the carry pass and completed in
+    the x sweep: the same steps as the separate y sweep up to rounding, and
+    both match the oracle (FP64 plans keep the separate sweep either way)."""
+    n, d = shape
+    cfg = W.Config("t", n, d, 0.003, (1.0, 1.1, 0.8), 30.0, 12.0, True, 5, noise=1e-3, seed=12)
+    psi0 = W.noisy_gaussian(cfg)
+    outs = []
+    for fused in (1, 0):
+        _say(f"fused_y={fused} {n} {prec}")
+        plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=_dtype(torch_mod, prec))
+        plan.set("fused_y", fused)
+        assert plan.fused_y == (bool(fused) and prec == "f32")  # FP32 imaginary time only
+        psi = plan.new_state(psi0)
+        plan.step(psi, cfg.steps)
+        outs.append(psi.cpu().numpy().astype(np.complex128))
+    ref = O.evolve(O.Params.from_config(cfg), psi0, cfg.steps)
+    e_f, e_s, e_fs = _rel(outs[0], ref), _rel(outs[1], ref), _rel(outs[0], outs[1])
+    _say(f"  fused {e_f:.2e} separate {e_s:.2e} fused-vs-separate {e_fs:.2e}")
+    assert max(e_f, e_s, e_fs) < TOL[prec]
