@@ -110,13 +110,24 @@ __global__ void __launch_bounds__(kRedThreads)
     partials += blockIdx.x * set_stride;
     if (out) out += (size_t)blockIdx.x * width;
     if (blockIdx.x > 0) sigma_out = nullptr;
+    constexpr int kBatch = 8;  // loads in flight per thread before the adds
     for (int w = 0; w < width; ++w) {
         double s = 0.0, c = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kRedThreads) {
-            const double v = partials[(size_t)b * width + w];
-            const double t = s + v;
-            c += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
-            s = t;
+        for (int b0 = threadIdx.x; b0 < nblocks; b0 += kBatch * kRedThreads) {
+            double vb[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                const int b = b0 + j * kRedThreads;
+                vb[j] = b < nblocks ? partials[(size_t)b * width + w] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; ++j) {
+                if (b0 + j * kRedThreads >= nblocks) break;
+                const double v = vb[j];
+                const double t = s + v;
+                c += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
+                s = t;
+            }
         }
         ss[threadIdx.x] = s + c;
         __syncthreads();
