@@ -331,6 +331,13 @@ bool use_fused_y(const Plan& p) {
 
 bool fused_y(const Plan& p) { return p.f32 ? use_fused_y<float>(p) : use_fused_y<double>(p); }
 
+// the fused y schedule also folds the norm reduction into the forward y FFT
+// when that pass is compiled with whole waves
+template <typename T>
+bool use_folded_norm(const Plan& p) {
+    return use_fused_y<T>(p) && fast_rows_sigma_ok<T>(p);
+}
+
 // nsteps steps in place on psi; with psi_in, the first step reads psi_in
 // instead (out of place) and, with phi_out, also writes Phi of psi_in's density.
 template <typename T>
@@ -342,17 +349,24 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
     void* car = use_fused_y<T>(p) ? p.phi : nullptr;
     const size_t car_bytes = (size_t)p.n[0] * (p.n[1] / 16) * p.n[2] * 2 * sizeof(T);  // one array
     const int nb_x = cn_strided_blocks(p, 0, car != nullptr);
+    // with the fused y schedule the previous step's norm is reduced inside the
+    // forward y FFT (block 0) and applied to Phi in the fused z pass; P1 then
+    // transforms the unscaled density
+    const bool fold = car && use_folded_norm<T>(p);
     for (int s = 0; s < nsteps; ++s) {
         const double a = amp ? amp[s] : 1.0;
         const double* sg = (p.imag && s > 0) ? sigma : nullptr;
         const void* src = (s == 0 && psi_in) ? psi_in : psi;
         void* phs = s == 0 ? phi_out : nullptr;
-        DGPE_PASS(t, 0, (launch_r2c_density<T>(p, src, sg)));
-        DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
+        DGPE_PASS(t, 0, (launch_r2c_density<T>(p, src, fold ? nullptr : sg)));
+        if (fold && sg)
+            DGPE_PASS(t, 1, (launch_rows<T>(p, false, p.red, nb_x, sigma)));
+        else
+            DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
         DGPE_PASS(t, 2, (launch_xmul<T>(p)));
         DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
         if (car && !phs) {
-            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, nullptr, car)));
+            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, nullptr, car, fold && sg)));
             DGPE_PASS(t, 5, (launch_cn_ycarry<T>(p, car)));
             DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.red,
                                                   (char*)car + 3 * car_bytes)));
@@ -361,7 +375,8 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
             DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
             DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr)));
         }
-        if (p.imag) DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb_x, sigma)));
+        if (p.imag && (!fold || s + 1 == nsteps))
+            DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb_x, sigma)));
     }
     if (p.imag && nsteps > 0) DGPE_HIP(launch_scale<T>(p, psi, sigma));
     return DGPE_OK;
@@ -381,6 +396,8 @@ void pass_bytes(const Plan& p, double b[DGPE_NPASS]) {
     b[5] = 2.0 * state;          // psi in place
     b[6] = 2.0 * state;
     if (fused_y(p)) {
+        const bool fold = p.f32 ? use_folded_norm<float>(p) : use_folded_norm<double>(p);
+        if (fold) b[1] += 8.0 * cn_strided_blocks(p, 0, true);  // the norm partials
         const double car = state / 16.0;  // one carry array [Nx][Ny/16][Nz]
         b[4] += 3.0 * car;                // + the three carry inputs
         b[5] = 5.0 * car;                 // carry pass: read 3, write the (c_d, c_x) pairs

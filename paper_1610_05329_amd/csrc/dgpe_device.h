@@ -290,6 +290,33 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     return r;
 }
 
+// Deterministic FP64 sum of n partials by one block (blockDim a multiple of
+// 64): each thread a strided Neumaier sum, its loads issued in batches of 8,
+// then block_sum.  The result is valid in thread 0; every thread must call.
+__device__ __forceinline__ double block_sum_partials(const double* __restrict__ partials, int n,
+                                                     double* scratch) {
+    constexpr int kBatch = 8;
+    const int nt = blockDim.x;
+    double s = 0.0, c = 0.0;
+    for (int b0 = threadIdx.x; b0 < n; b0 += kBatch * nt) {
+        double vb[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            const int b = b0 + j * nt;
+            vb[j] = b < n ? partials[b] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; ++j) {
+            if (b0 + j * nt >= n) break;
+            const double v = vb[j];
+            const double t = s + v;
+            c += (fabs(s) >= fabs(v)) ? (s - t) + v : (v - t) + s;
+            s = t;
+        }
+    }
+    return block_sum(s + c, scratch);
+}
+
 }  // namespace dgpe
 
 namespace dgpe {

@@ -77,17 +77,23 @@ hipError_t launch_r2c_density(const Plan& p, const void* psi, const double* sigm
 template <typename T>
 hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin, const void* phin,
                                 double amp, double* partials, int* nblocks);
+// npart (forward, compiled pass only): block 0 also reduces nnpart FP64 norm
+// partials into *sigma_out = 1 / (sum dV)
 template <typename T>
-hipError_t launch_rows(const Plan& p, bool inverse);
+hipError_t launch_rows(const Plan& p, bool inverse, const double* npart = nullptr, int nnpart = 0,
+                       double* sigma_out = nullptr);
 template <typename T>
 hipError_t launch_xmul(const Plan& p);
 template <typename T>
 // P5 from psi_in to psi_out (may be the same buffer); phi_out (optional)
 // receives Phi of psi_in's density; ycar (optional, imaginary time, the
 // compiled pass only): also solve the y axis in 16-line segments with zero
-// carries, writing the three carry inputs [3][Nx][Ny/16][Nz] there
+// carries, writing the three carry inputs [3][Nx][Ny/16][Nz] there;
+// phi_sigma (compiled pass only): the spectrum holds the unscaled density and
+// Phi is multiplied by sigma here
 hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                           double amp, void* phi_out = nullptr, void* ycar = nullptr);
+                           double amp, void* phi_out = nullptr, void* ycar = nullptr,
+                           bool phi_sigma = false);
 template <typename T>
 hipError_t launch_c2r_phi(const Plan& p, void* phi_out);
 template <typename T>
@@ -138,7 +144,10 @@ int cn_strided_blocks(const Plan& p, int axis, bool ycarry = false);
 // Two-factor register FFT passes (k_fft2.hip); false when the length has no
 // compiled fast path (the caller then uses the generic Stockham kernel).
 template <typename T>
-bool fast_rows(const Plan& p, bool inverse);
+bool fast_rows(const Plan& p, bool inverse, const double* npart, int nnpart, double* sigma_out);
+// the compiled forward rows pass can reduce the norm partials (whole waves)
+template <typename T>
+bool fast_rows_sigma_ok(const Plan& p);
 template <typename T>
 bool fast_xmul(const Plan& p);
 template <typename T>
@@ -153,7 +162,7 @@ template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
 template <typename T>
 bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                   double amp, void* phi_out, void* ycar);
+                   double amp, void* phi_out, void* ycar, bool phi_sigma);
 // the compiled fused z pass can start the y solve for this plan (blocks of whole
 // 16-line y segments, imaginary time)
 template <typename T>

@@ -23,10 +23,14 @@ constexpr int rows_per_block() {
 // ---------------------------------------------------------------------------
 // P2 / P4: FFT along contiguous rows of length L = R1 R2 (the y axis of S).
 // Lanes: t fastest (t < R1 threads per row), NB rows per block.
+// With npart (imaginary time), block 0 also turns the previous x sweep's norm
+// partials into sigma = 1 / (sum dV) after its rows, for the fused z pass of
+// this step: the reduction then needs no launch of its own.
 // ---------------------------------------------------------------------------
 template <typename T, int R1, int R2, bool INV>
 __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
-    k_rows2(cx<T>* __restrict__ spec, int nrows, const cx<T>* __restrict__ tw) {
+    k_rows2(cx<T>* __restrict__ spec, int nrows, const cx<T>* __restrict__ tw,
+            const double* __restrict__ npart, int nnpart, double dV, double* __restrict__ sigma_out) {
     constexpr int L = R1 * R2;
     constexpr int NB = rows_per_block<T, R1, L>();
     constexpr int SB = R2 * (R1 + 1);
@@ -60,6 +64,11 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
         rdft<T, R1, INV>(w);
 #pragma unroll
         for (int k = 0; k < R1; ++k) base[t + R2 * k] = w[k];
+    }
+    if (npart && blockIdx.x == 0) {  // block-uniform
+        __shared__ double sred[(rows_per_block<T, R1, L>() * R1 + 63) / 64];
+        const double sum = block_sum_partials(npart, nnpart, sred);
+        if (tid == 0) sigma_out[0] = 1.0 / (sum * dV);
     }
 }
 
@@ -589,7 +598,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
                 const double* __restrict__ sigma, Phys2 ph,
                 const cx<double>* __restrict__ ytab, cx<double> kappay64,
-                cx<T>* __restrict__ ycar) {
+                cx<T>* __restrict__ ycar, int phi_sigma) {
     using A = cn_acc_t<T, RC>;
     using G = Step2Geom<T, R1, R2, SZ>;
     constexpr int M = G::M, Nz = G::Nz, nseg = G::nseg, LPW = G::LPW, U = G::U, NU = G::NU;
@@ -680,6 +689,8 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     // nonlinear step in the load layout (pre-step density, lazily normalised)
     const double sg = sigma ? sigma[0] : 1.0;
     const T sig = T(sg), rs = T(sqrt(sg));
+    // phi_sigma: the spectrum is of the unscaled density (sigma applied here)
+    const T phs = phi_sigma ? sig : T(1);
     const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
     const T xx = T(x - ph.hx) * T(ph.dx);
     const T vx = T(ph.cx) * xx * xx;
@@ -691,7 +702,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
         const T yy = T(y0 + wv * LPW + lw - ph.hy) * T(ph.dy);
         const T vxy = vx + T(ph.cy) * yy * yy;
         const int m = e0 >> 1;
-        const cx<T> fv = prow[lw * PS + m + (m >> 3)];
+        const cx<T> fv = phs * prow[lw * PS + m + (m >> 3)];
         if constexpr (PHI) {  // Phi of the pre-step density, for the adjoint
             if constexpr (U == 2) *reinterpret_cast<cx<T>*>(phi_out + wl + c0) = fv;
             else phi_out[wl + c0] = (e0 & 1) ? fv.y : fv.x;
@@ -808,22 +819,43 @@ int fast_rows_per_block(int L) {
 }
 
 template <typename T>
-bool fast_rows(const Plan& p, bool inverse) {
+int fast_rows_threads(int L) {
+    switch (L) {
+#define DGPE_CASE(A, B) \
+    case A * B: return rows_per_block<T, A, A * B>() * A;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return 0;
+    }
+}
+
+template <typename T>
+bool fast_rows_sigma_ok(const Plan& p) {
+    const int nt = fast_rows_threads<T>(p.n[1]);
+    return nt > 0 && nt % 64 == 0;
+}
+
+template <typename T>
+bool fast_rows(const Plan& p, bool inverse, const double* npart, int nnpart, double* sigma_out) {
     const int L = p.n[1];
     const Split2 s = fast_split(L);
     if (!s.r1) return false;
+    if (npart && (inverse || !fast_rows_sigma_ok<T>(p))) return false;
     const int nb = fast_rows_per_block<T>(L);
     const int nrows = (p.n[2] / 2 + 1) * p.n[0];
     const int blocks = (nrows + nb - 1) / nb;
+    const double dV = p.d[0] * p.d[1] * p.d[2];
     switch (L) {
 #define DGPE_CASE(A, B)                                                                              \
     case A * B:                                                                                      \
         if (inverse)                                                                                 \
             hipLaunchKernelGGL((k_rows2<T, A, B, true>), dim3(blocks), dim3(nb * A), 0, p.stream,   \
-                               (cx<T>*)p.spec, nrows, (const cx<T>*)p.tw[1]);                        \
+                               (cx<T>*)p.spec, nrows, (const cx<T>*)p.tw[1], nullptr, 0, dV,        \
+                               nullptr);                                                             \
         else                                                                                         \
             hipLaunchKernelGGL((k_rows2<T, A, B, false>), dim3(blocks), dim3(nb * A), 0, p.stream,  \
-                               (cx<T>*)p.spec, nrows, (const cx<T>*)p.tw[1]);                        \
+                               (cx<T>*)p.spec, nrows, (const cx<T>*)p.tw[1], npart, nnpart, dV,     \
+                               sigma_out);                                                           \
         return true;
         DGPE_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
@@ -972,7 +1004,7 @@ bool fast_c2r_step_yfused_ok(const Plan& p) {
 
 template <typename T>
 bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                   double amp, void* phi_out, void* ycar) {
+                   double amp, void* phi_out, void* ycar, bool phi_sigma) {
     const int M = p.n[2] / 2;
     const int nb = fast_c2r_step_lines<T>(p);
     if (!nb) return false;
@@ -993,7 +1025,8 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
                        dim3(step2_threads<T, A, B, 16>()), 0, p.stream, (const cx<T>*)psi_in,       \
                        (cx<T>*)psi_out, (T*)phi_out,                                                \
                        (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],                \
-                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph, ytab, kappay, (cx<T>*)ycar)
+                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph, ytab, kappay, (cx<T>*)ycar, \
+                       phi_sigma ? 1 : 0)
 #define DGPE_CASE(A, B)                                         \
     case A * B:                                                 \
         if (p.imag) {                                           \
@@ -1013,7 +1046,7 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
 }
 
 #define DGPE_INST(T)                                                 \
-    template bool fast_rows<T>(const Plan&, bool);                   \
+    template bool fast_rows<T>(const Plan&, bool, const double*, int, double*); \
     template bool fast_xmul<T>(const Plan&);                         \
     template bool fast_r2c<T>(const Plan&, const void*, const double*); \
     template bool fast_r2c_adj<T>(const Plan&, const void*, const void*, const void*, double, \
@@ -1021,7 +1054,8 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
     template bool fast_c2r_adjupd<T>(const Plan&, void*, const void*, const void*, double); \
     template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*, \
-                                   void*);                                                        \
+                                   void*, bool);                                                  \
+    template bool fast_rows_sigma_ok<T>(const Plan&);                                             \
     template bool fast_c2r_step_yfused_ok<T>(const Plan&);
 DGPE_INST(float)
 DGPE_INST(double)

@@ -561,8 +561,10 @@ hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin,
 }
 
 template <typename T>
-hipError_t launch_rows(const Plan& p, bool inverse) {
-    if (p.fast && fast_rows<T>(p, inverse)) return hipGetLastError();
+hipError_t launch_rows(const Plan& p, bool inverse, const double* npart, int nnpart,
+                       double* sigma_out) {
+    if (p.fast && fast_rows<T>(p, inverse, npart, nnpart, sigma_out)) return hipGetLastError();
+    if (npart) return hipErrorInvalidValue;  // only the compiled pass reduces the norm
     const int L = p.n[1];
     const int es = (1 << p.lc.logB_y) + 1;
     const int nrows = (p.n[2] / 2 + 1) * p.n[0];
@@ -594,10 +596,11 @@ hipError_t launch_xmul(const Plan& p) {
 
 template <typename T>
 hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
-                           double amp, void* phi_out, void* ycar) {
-    if (p.fast && fast_c2r_step<T>(p, psi_in, psi_out, sigma, amp, phi_out, ycar))
+                           double amp, void* phi_out, void* ycar, bool phi_sigma) {
+    if (p.fast && fast_c2r_step<T>(p, psi_in, psi_out, sigma, amp, phi_out, ycar, phi_sigma))
         return hipGetLastError();
-    if (ycar) return hipErrorInvalidValue;  // only the compiled fused pass starts the y solve
+    // only the compiled fused pass starts the y solve or scales Phi by sigma
+    if (ycar || phi_sigma) return hipErrorInvalidValue;
     const int es = (1 << p.lc.logB_z) + 1;
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
@@ -655,10 +658,10 @@ hipError_t launch_ukern(const Plan& p) {
     template hipError_t launch_r2c_density<T>(const Plan&, const void*, const double*);            \
     template hipError_t launch_r2c_adjoint_s<T>(const Plan&, const void*, const void*, const void*, \
                                                 double, double*, int*);                            \
-    template hipError_t launch_rows<T>(const Plan&, bool);                                         \
+    template hipError_t launch_rows<T>(const Plan&, bool, const double*, int, double*);           \
     template hipError_t launch_xmul<T>(const Plan&);                                               \
     template hipError_t launch_c2r_step<T>(const Plan&, const void*, void*, const double*, double, \
-                                           void*, void*);      \
+                                           void*, void*, bool); \
     template hipError_t launch_c2r_phi<T>(const Plan&, void*);                                     \
     template hipError_t launch_ukern<T>(const Plan&);
 DGPE_INST(float)
