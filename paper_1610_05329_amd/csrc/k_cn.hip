@@ -271,6 +271,107 @@ __global__ void __launch_bounds__(64) k_cn_ycarry(cx<T>* __restrict__ car, int N
         }
 }
 
+// The same carries with each column's K segments split between two lanes of
+// one wave (lane l: segments [0, H), lane l + 32: [H, K), H = ceil(K/2)), so
+// that twice as many waves share the latency of the loads.  Each lane runs its
+// part of a chain from a zero carry; the upper half's forward values are then
+// completed with prod PEND times the lower half's end value, and the lower
+// half's backward values with prod QBEG times the upper half's end value (one
+// shuffle each).  Same layouts and tables as k_cn_ycarry; 32 columns per block.
+template <typename T, bool RC, int KH>
+__global__ void __launch_bounds__(64) k_cn_ycarry2(cx<T>* __restrict__ car, int Nx, int Ny, int Nz,
+                                                  const cx<double>* __restrict__ ytab, int lzb) {
+    using A = cn_acc_t<T, RC>;
+    constexpr int KM = 2 * KH;
+    __shared__ cx<A> sf[4][KM];
+    const int K = Ny >> 4, H = (K + 1) >> 1;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int half = tid >> 5;
+    const int g = blockIdx.x * 32 + (tid & 31);
+    const int tq = min(tid / KM, 3), tk = min(tid % KM, K - 1);
+    const int tix = tq == 0 ? TAB_ALPHA * Ny + 16 * tk + 15
+                  : tq == 1 ? TAB_PEND * Ny + tk
+                  : tq == 2 ? TAB_E * Ny + 16 * tk
+                            : TAB_QBEG * Ny + tk;
+    const cx<double> tv = tab_at<RC>(ytab, tix);
+    const bool act = g < Nx * Nz;
+    const int gg = act ? g : 0;
+    const int x = gg / Nz, z = gg - x * Nz;
+    const int k0 = half ? H : 0, k1 = half ? K : H;
+    const size_t cst = (size_t)Nx * K * Nz;
+    cx<T>* c0 = car + (size_t)x * K * Nz + z;
+    cx<T> dl[KH], xf[KH], uf[KH];
+#pragma unroll
+    for (int j = 0; j < KH; ++j)
+        if (k0 + j < k1) {
+            const size_t o = (size_t)(k0 + j) * Nz;
+            dl[j] = c0[o];
+            xf[j] = c0[cst + o];
+            uf[j] = c0[2 * cst + o];
+        }
+    const cx<A> zero = {A(0), A(0)}, one = {A(1), A(0)};
+    const cx<A> ufend = k1 < K ? widen<A>(c0[2 * cst + (size_t)k1 * Nz]) : zero;
+    if (tid < 4 * KM) sf[tq][tid % KM] = narrow_tab<A>(tv);
+    __syncthreads();
+    // forward, from a zero carry at k0
+    cx<A> cd[KH];
+    cx<A> c = zero;
+#pragma unroll
+    for (int j = 0; j < KH; ++j)
+        if (k0 + j < k1) {
+            const int k = k0 + j;
+            cd[j] = c;
+            const cx<A> ufn = (k + 1 < k1) ? widen<A>(uf[j + 1 < KH ? j + 1 : j]) : ufend;
+            c = widen<A>(dl[j]) + kmul<RC>(sf[0][k], ufn) + kmul<RC>(sf[1][k], c);
+        }
+    const cx<A> cin = shfl_up_c(c, 32, 64);  // the lower half's end value, on the upper lanes
+    if (half) {
+        cx<A> pp = one;
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if (k0 + j < k1) {
+                cd[j] = cd[j] + kmul<RC>(pp, cin);
+                pp = kmul<RC>(sf[1][k0 + j], pp);
+            }
+    }
+    // backward, from a zero carry at k1 - 1
+    cx<A> cx_[KH];
+    c = zero;
+#pragma unroll
+    for (int j = KH - 1; j >= 0; --j)
+        if (k0 + j < k1) {
+            const int k = k0 + j;
+            cx_[j] = c;
+            c = widen<A>(xf[j]) + kmul<RC>(sf[2][k], cd[j]) + kmul<RC>(sf[3][k], c);
+        }
+    const cx<A> xin = shfl_down_c(c, 32, 64);  // the upper half's end value, on the lower lanes
+    if (!half) {
+        cx<A> qq = one;
+#pragma unroll
+        for (int j = KH - 1; j >= 0; --j)
+            if (k0 + j < k1) {
+                cx_[j] = cx_[j] + kmul<RC>(qq, xin);
+                qq = kmul<RC>(sf[3][k0 + j], qq);
+            }
+    }
+    if (!act) return;
+    const int zbm = (1 << lzb) - 1;
+    const size_t ktile = (size_t)(Nz >> lzb) * Nx << lzb;  // pairs per segment
+    cx<T>* pr = car + 3 * cst + ((((size_t)(z >> lzb) * Nx + x) << lzb) + (z & zbm)) * 2;
+#pragma unroll
+    for (int j = 0; j < KH; ++j)
+        if (k0 + j < k1) {
+            cx<T> t2[2] = {to_store<T>(cd[j]), to_store<T>(cx_[j])};
+            cx<T>* dst = pr + (size_t)(k0 + j) * ktile * 2;
+            if constexpr (sizeof(T) == 4) {
+                store_unit<T>(dst, t2);
+            } else {
+                dst[0] = t2[0];
+                dst[1] = t2[1];
+            }
+        }
+}
+
 // Standalone z sweep of B = 2^logB contiguous lines, staged through LDS.
 // LDS: P (Nz rows, storage type) | carries (arithmetic type) | pend | qbeg
 template <typename T, int SZ, bool RC, bool GUARD>
@@ -465,7 +566,11 @@ hipError_t launch_cn_ycarry(const Plan& p, void* car) {
                        (cx<T>*)car, p.n[0], p.n[1], p.n[2], ytab, lzb)
     if (K <= 4) DGPE_YC(4);
     else if (K <= 8) DGPE_YC(8);
-    else DGPE_YC(16);
+    else if (p.n[2] % 32)
+        DGPE_YC(16);
+    else  // two lanes per column
+        hipLaunchKernelGGL((k_cn_ycarry2<T, true, 8>), dim3((p.n[0] * p.n[2] + 31) / 32), dim3(64), 0,
+                           p.stream, (cx<T>*)car, p.n[0], p.n[1], p.n[2], ytab, lzb);
 #undef DGPE_YC
     return hipGetLastError();
 }
