@@ -158,7 +158,7 @@ bool layout(const int n[3], bool f32, size_t offs[OFF_END + 1], Launch* lc_out,
     size_t sz[OFF_END];
     sz[OFF_SPEC] = (nz / 2 + 1) * nx * ny * csz;
     sz[OFF_PHI] = nx * ny * nz * rsz;
-    sz[OFF_UK] = (nz / 2 + 1) * ny * (nx / 2 + 1) * rsz;
+    sz[OFF_UK] = (nz / 2 + 1) * (ny / 2 + 1) * (nx / 2 + 1) * rsz;
     sz[OFF_TWX] = nx * csz;
     sz[OFF_TWY] = ny * csz;
     sz[OFF_TWZ] = (nz / 2) * csz;
@@ -387,7 +387,7 @@ void pass_bytes(const Plan& p, double b[DGPE_NPASS]) {
     const double nt = (double)p.n[0] * p.n[1] * p.n[2];
     const double state = 2.0 * s * nt;
     const double spec = 2.0 * s * (double)p.n[0] * p.n[1] * (p.n[2] / 2 + 1);
-    const double uk = s * (double)(p.n[0] / 2 + 1) * p.n[1] * (p.n[2] / 2 + 1);
+    const double uk = s * (double)(p.n[0] / 2 + 1) * (p.n[1] / 2 + 1) * (p.n[2] / 2 + 1);
     b[0] = state + spec;         // read psi, write S
     b[1] = 2.0 * spec;           // S in place
     b[2] = 2.0 * spec + uk;      // S in place + kernel table

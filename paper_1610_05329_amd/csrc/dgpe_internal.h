@@ -55,7 +55,7 @@ struct Plan {
     size_t ws_bytes;
     void* spec;         // [Nz/2+1][Nx][Ny] complex
     void* phi;          // [Nx][Ny][Nz] real (observables / adjoint scratch)
-    void* ukern;        // [Nz/2+1][Nx/2+1][Ny] real, U_R / Nt (even in kx)
+    void* ukern;        // [Nz/2+1][Nx/2+1][Ny/2+1] real, U_R / Nt (even in kx and ky)
     void* tw[3];        // twiddles W_L^m for the x, y FFTs (L = Nx, Ny) and the z FFT (L = Nz/2)
     void* twr2c;        // W_Nz^k, k = 0..Nz/2
     void* cntab[3][2];  // per axis: [0] forward A, [1] conj(A) (adjoint)

@@ -74,8 +74,8 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 
 // ---------------------------------------------------------------------------
 // P3: FFT along x (stride Ny) of NB adjacent columns at one kz, multiply by
-// U_R/Nt (table [kz][|kx|][ky]: each entry read once per step), inverse FFT
-// along x.
+// U_R/Nt (table [kz][|kx|][|ky|]: each entry read by the blocks of ky and
+// Ny - ky, which run together on one XCD), inverse FFT along x.
 // Lanes: b fastest (NB columns), t < R1 threads per column.
 // ---------------------------------------------------------------------------
 template <typename T, int R1, int R2>
@@ -102,13 +102,15 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 #pragma unroll
     for (int n = 0; n < R2; ++n) v[n] = base[(size_t)(t + R1 * n) * Ny];
     // after the forward FFT thread t < R2 holds X[kx = t + R2 k]; the kernel is
-    // even in kx: table [kz][|kx|][ky] (threads t >= R2 read t = R2 - 1's)
-    const T* ucol = ukern + (size_t)kz * (L / 2 + 1) * Ny + y0 + b;
+    // even in kx and ky: table [kz][|kx|][|ky|] (threads t >= R2 read t =
+    // R2 - 1's)
+    const int hy = Ny / 2 + 1;
+    const T* ucol = ukern + (size_t)kz * (L / 2 + 1) * hy + min(y0 + b, Ny - y0 - b);
     T uk[R1];
 #pragma unroll
     for (int k = 0; k < R1; ++k) {
         const int kx0 = min(t, R2 - 1) + R2 * k;
-        uk[k] = ucol[(size_t)min(kx0, L - kx0) * Ny];
+        uk[k] = ucol[(size_t)min(kx0, L - kx0) * hy];
     }
     tab_stage(rtw, stw, tid, [](int i) { return i; });
     __syncthreads();

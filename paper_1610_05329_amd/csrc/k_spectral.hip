@@ -263,11 +263,12 @@ __global__ void __launch_bounds__(256) DGPE_FFT_OCC k_xmul(cx<T>* __restrict__ s
     }
     __syncthreads();
     lds_fft<T, false, kEmax>(buf, ES, fx, logB, stw, tid, nthr);
-    const T* ucol = ukern + (size_t)kz * (Nx / 2 + 1) * Ny + y0;
+    const int hy = Ny / 2 + 1;
+    const T* ucol = ukern + (size_t)kz * (Nx / 2 + 1) * hy;
     for (int g = tid; g < total; g += nthr) {
         const int e = g >> logB, b = g & (B - 1);
-        const int kx = min(e, Nx - e);
-        const T u = ucol[(size_t)kx * Ny + b];
+        const int kx = min(e, Nx - e), ky = min(y0 + b, Ny - y0 - b);
+        const T u = ucol[(size_t)kx * hy + ky];
         cx<T>& c = buf[e * ES + b];
         c = u * c;
     }
@@ -474,14 +475,13 @@ __global__ void __launch_bounds__(256) k_c2r_phi(T* __restrict__ phi, const cx<T
 template <typename T>
 __global__ void k_ukern(T* __restrict__ out, int Nx, int Ny, int Nz, double dkx, double dky,
                         double dkz, double R, double inv_nt) {
-    const int hx = Nx / 2 + 1, hz = Nz / 2 + 1;
-    const size_t total = (size_t)hx * Ny * hz;
+    const int hx = Nx / 2 + 1, hy = Ny / 2 + 1, hz = Nz / 2 + 1;
+    const size_t total = (size_t)hx * hy * hz;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
          i += (size_t)gridDim.x * blockDim.x) {
-        const int kyi = int(i % Ny);
-        const int kx = int((i / Ny) % hx);
-        const int kz = int(i / ((size_t)hx * Ny));
-        const int ky = min(kyi, Ny - kyi);
+        const int ky = int(i % hy);
+        const int kx = int((i / hy) % hx);
+        const int kz = int(i / ((size_t)hx * hy));
         const double qx = kx * dkx, qy = ky * dky, qz = kz * dkz;
         const double k2 = qx * qx + qy * qy + qz * qz;
         double u = 0.0;
@@ -646,7 +646,7 @@ template <typename T>
 hipError_t launch_ukern(const Plan& p) {
     const double two_pi = 2.0 * M_PI;
     const double nt = (double)p.n[0] * p.n[1] * p.n[2];
-    const size_t total = (size_t)(p.n[0] / 2 + 1) * p.n[1] * (p.n[2] / 2 + 1);
+    const size_t total = (size_t)(p.n[0] / 2 + 1) * (p.n[1] / 2 + 1) * (p.n[2] / 2 + 1);
     const int blocks = (int)std::min<size_t>((total + 255) / 256, 65535);
     hipLaunchKernelGGL((k_ukern<T>), dim3(blocks), dim3(256), 0, p.stream, (T*)p.ukern, p.n[0],
                        p.n[1], p.n[2], two_pi / (p.n[0] * p.d[0]), two_pi / (p.n[1] * p.d[1]),
