@@ -246,6 +246,8 @@ FUSED_Y_SHAPES = [
     ((24, 96, 128), (0.35, 0.2, 0.2)),   # 32 lines per block (2 segments), 6 segments
     ((24, 32, 64), (0.4, 0.4, 0.3)),     # 32 lines per block, half the block's waves idle
     ((12, 256, 256), (0.5, 0.08, 0.1)),  # 16 segments, x lines shorter than a segment
+    ((8, 16, 256), (0.5, 0.5, 0.1)),     # one segment: every carry is zero
+    ((8, 144, 256), (0.5, 0.15, 0.1)),   # 9 segments: the carry chains split 5 + 4
 ]
 
 
