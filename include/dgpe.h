@@ -81,9 +81,9 @@ typedef enum {
 #define DGPE_PARAM_DT 5
 #define DGPE_PARAM_REAL_TIME 6 /* value 1: real time, 0: imaginary time */
 #define DGPE_PARAM_FAST_FFT 7  /* 1 (default): compiled two-factor FFT passes where available; 0: generic passes only */
-#define DGPE_PARAM_FUSED_Y 8   /* 1 (default): in FP32 imaginary time, the fused z pass also solves the y
-                                  axis in 16-line segments and pass 5 joins them (see the pass list); 0:
-                                  the separate y sweep.  Same result to rounding either way */
+#define DGPE_PARAM_FUSED_Y 8   /* 1 (default): in imaginary time, the fused z pass also solves the y axis
+                                  in 16-line segments and pass 5 joins them (see the pass list); 0: the
+                                  separate y sweep.  Same result to rounding either way */
 
 /* adjoint objectives */
 #define DGPE_OBJ_ENERGY 0
@@ -180,8 +180,8 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
  *   3 inverse FFT along y        4 C2R along z + nonlinear phase + CN along z
  *   5 CN along y                 6 CN along x (+ norm partials, imaginary time)
  *   7 norm reduction (imaginary time)
- * With DGPE_PARAM_FUSED_Y in effect (FP32 imaginary time, compiled fused
- * pass, Ny a multiple of 16 up to 256): pass 4 also solves y in 16-line
+ * With DGPE_PARAM_FUSED_Y in effect (imaginary time, compiled fused pass,
+ * Ny a multiple of 16 up to 256, state under 4 GiB): pass 4 also solves y in 16-line
  * segments with zero carries, pass 5 is the segment carry pass, and pass 6
  * adds the carries before the x solve; the norm of one step is then reduced
  * inside pass 1 of the next (pass 7 runs once, after the last step). */

@@ -315,18 +315,16 @@ struct PassTimer {
 
 // The y solve starts inside the fused z pass (16-line segments, zero carries),
 // a carry pass joins the segments and the x sweep adds the carries while it
-// loads: FP32 imaginary time, compiled fused pass, Ny / 16 <= 16 segments,
-// state under 4 GiB (32-bit offsets in the x sweep).  The carry inputs
+// loads: imaginary time, compiled fused pass, Ny / 16 <= 16 segments, state
+// under 4 GiB (32-bit offsets in the x sweep).  The carry inputs
 // ([3][Nx][Ny/16][Nz] complex) and the carry pairs (the same count times 2),
 // together 5/16 of the state's bytes, live in the Phi buffer (half the
 // state's bytes), which stepping does not otherwise use in imaginary time.
 template <typename T>
 bool use_fused_y(const Plan& p) {
     const size_t state = (size_t)p.n[0] * p.n[1] * p.n[2] * 2 * sizeof(T);
-    // FP32 only: the FP64 x sweep with the carries added runs at two waves
-    // per SIMD and loses more than the y sweep it replaces
-    return sizeof(T) == 4 && p.fuse_y && p.fast && p.imag && p.n[1] / 16 <= 16 &&
-           state < (size_t(1) << 32) && fast_c2r_step_yfused_ok<T>(p);
+    return p.fuse_y && p.fast && p.imag && p.n[1] / 16 <= 16 && state < (size_t(1) << 32) &&
+           fast_c2r_step_yfused_ok<T>(p);
 }
 
 bool fused_y(const Plan& p) { return p.f32 ? use_fused_y<float>(p) : use_fused_y<double>(p); }

@@ -254,10 +254,10 @@ FUSED_Y_SHAPES = [
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", FUSED_Y_SHAPES, ids=lambda s: "x".join(map(str, s[0])))
 def test_fused_y_schedule_matches_oracle(dg, torch_mod, shape, prec):
-    """FP32 imaginary time with the y solve started in the fused z pass
-    (16-line segments, zero carries), joined by the carry pass and completed in
-    the x sweep: the same steps as the separate y sweep up to rounding, and
-    both match the oracle (FP64 plans keep the separate sweep either way)."""
+    """Imaginary time with the y solve started in the fused z pass (16-line
+    segments, zero carries), joined by the carry pass and completed in the x
+    sweep: the same steps as the separate y sweep up to rounding, and both
+    match the oracle."""
     n, d = shape
     cfg = W.Config("t", n, d, 0.003, (1.0, 1.1, 0.8), 30.0, 12.0, True, 5, noise=1e-3, seed=12)
     psi0 = W.noisy_gaussian(cfg)
@@ -266,7 +266,7 @@ def test_fused_y_schedule_matches_oracle(dg, torch_mod, shape, prec):
         _say(f"fused_y={fused} {n} {prec}")
         plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=_dtype(torch_mod, prec))
         plan.set("fused_y", fused)
-        assert plan.fused_y == (bool(fused) and prec == "f32")  # FP32 imaginary time only
+        assert plan.fused_y == bool(fused)
         psi = plan.new_state(psi0)
         plan.step(psi, cfg.steps)
         outs.append(psi.cpu().numpy().astype(np.complex128))
