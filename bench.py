@@ -137,9 +137,10 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--adjoint-steps", type=int, default=40)
-    ap.add_argument("--workload", choices=["C3", "C5", "ADJ"], default="C3",
-                    help="configuration of --profile-run (the JSON line always uses C3); ADJ = "
-                         "the FP32 real-time adjoint variant of C3 (--steps forward steps, "
+    ap.add_argument("--workload", choices=["imag_256cubed", "real_512x512x256", "adjoint_256cubed"],
+                    default="imag_256cubed",
+                    help="workload of --profile-run (the JSON line always uses imag_256cubed); "
+                         "adjoint_256cubed = the FP32 real-time adjoint on that grid (--steps forward steps, "
                          "checkpoints every 10)")
     args = ap.parse_args()
 
@@ -154,8 +155,8 @@ def main():
         print("\n".join(out))
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU slab decomposition "
-              "is a design, not an implementation (see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only; the multi-GPU slab decomposition is designed "
+              "but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -173,8 +174,8 @@ def main():
         log(f"copy calibration: 5 copies of {n * 4} bytes")
         return
 
-    if args.profile_run and args.workload == "ADJ":
-        cfg = W.CONFIGS["C3"]
+    if args.profile_run and args.workload == "adjoint_256cubed":
+        cfg = W.CONFIGS["imag_256cubed"]
         plan_a = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True,
                          dtype=torch.complex64)
         psia = plan_a.new_state(W.noisy_gaussian(cfg))
@@ -184,7 +185,7 @@ def main():
         torch.cuda.synchronize()
         log("[bench] adjoint profile run done")
         return
-    cfg = W.CONFIGS[args.workload if args.profile_run else "C3"]
+    cfg = W.CONFIGS[args.workload if args.profile_run else "imag_256cubed"]
     log(f"[bench] workload {cfg.n} {'imaginary' if cfg.imag else 'real'} time; preparing seeded state")
     psi0 = W.noisy_gaussian(cfg)
     plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=not cfg.imag,
@@ -258,17 +259,18 @@ def main():
         del plan_a, psia, out
         torch.cuda.empty_cache()
         # 512 x 512 x 256 FP32 real time (the large anisotropic workload)
-        c5 = W.CONFIGS["C5"]
-        plan5 = dg.Plan(c5.n, c5.d, c5.dt, c5.trap, c5.g, c5.gd, real_time=True, dtype=torch.complex64)
-        init5 = plan5.new_state(W.noisy_gaussian(c5))
-        psi5 = init5.clone()
-        n5 = 20
-        w5, _ = timed_steps(torch, plan5, psi5, init5, n5, 5)
-        b5 = sum(plan5.pass_bytes().values())
-        variants["c5_f32_real"] = {"value": c5.npoints * n5 / w5, "ms_per_step": w5 * 1e3 / n5,
-                                   "grid": list(c5.n), "step_effective_GBs": round(b5 * n5 / w5 / 1e9, 1)}
-        log(f"[bench] C5 512x512x256 FP32 real time: {w5 * 1e3 / n5:.3f} ms/step")
-        del plan5, psi5, init5
+        big = W.CONFIGS["real_512x512x256"]
+        plan_big = dg.Plan(big.n, big.d, big.dt, big.trap, big.g, big.gd, real_time=True, dtype=torch.complex64)
+        init_big = plan_big.new_state(W.noisy_gaussian(big))
+        psi_big = init_big.clone()
+        n_big = 20
+        w_big, _ = timed_steps(torch, plan_big, psi_big, init_big, n_big, 5)
+        b_big = sum(plan_big.pass_bytes().values())
+        variants["real_512x512x256_f32"] = {
+            "value": big.npoints * n_big / w_big, "ms_per_step": w_big * 1e3 / n_big,
+            "grid": list(big.n), "step_effective_GBs": round(b_big * n_big / w_big / 1e9, 1)}
+        log(f"[bench] 512x512x256 FP32 real time: {w_big * 1e3 / n_big:.3f} ms/step")
+        del plan_big, psi_big, init_big
         torch.cuda.empty_cache()
 
     cpu = None

@@ -1,18 +1,18 @@
 """Writes full-size oracle records for the GPU parity tests (calls only the
 oracle and the seeded input module; minutes of CPU time each).
 
-  c3  256^3 imaginary time (dx 0.1, dt 0.001, trap (1, 1, 0.5), g 100, gd 60),
+  imag_256cubed    256^3 imaginary time (dx 0.1, dt 0.001, trap (1, 1, 0.5), g 100, gd 60),
       20 steps from the seeded noisy Gaussian: observables and 512 sampled
       state values.  (These parameters collapse after about 90 steps; the
       record stays on the regular part of the trajectory.)
-  c2  128^3: 200 imaginary-time steps at gd = 15 from the trap Gaussian, then
+  quench_128cubed  128^3: 200 imaginary-time steps at gd = 15 from the trap Gaussian, then
       the quench gd -> 20 and 1000 real-time steps (dt 0.002): observables at
       the quench and at the end, and 512 sampled state values.
-  c4  96^3: 500 imaginary-time steps (dt 0.002, gd 15) from the trap Gaussian
+  adjoint_96cubed  96^3: 500 imaginary-time steps (dt 0.002, gd 15) from the trap Gaussian
       as psi0, then the adjoint of the final energy through 400 real-time
       steps with the trap amplitude on 40 seeded knots in [0.8, 1.2).
 
-Usage: python tests/golden/make_fullsize_golden.py c3|c2|c4
+Usage: python tests/golden/make_fullsize_golden.py imag_256cubed|quench_128cubed|adjoint_96cubed
 """
 import json
 import os
@@ -57,28 +57,28 @@ def knot_amplitudes(knots, nsteps, dt):
     return out
 
 
-def make_c3():
-    cfg = W.CONFIGS["C3"]
+def make_imag_256cubed():
+    cfg = W.CONFIGS["imag_256cubed"]
     steps = 20
     p = O.Params.from_config(cfg)
     psi = O.evolve(p, W.noisy_gaussian(cfg), steps)
-    return {"config": "C3", "steps": steps, "observables": obs(p, psi), "samples": samples(psi, 33)}
+    return {"config": "imag_256cubed", "steps": steps, "observables": obs(p, psi), "samples": samples(psi, 33)}
 
 
-def make_c2():
-    cfg = W.CONFIGS["C2"]
+def make_quench_128cubed():
+    cfg = W.CONFIGS["quench_128cubed"]
     prep_steps, steps = 200, 1000
     prep = O.Params.from_config(cfg, gd=15.0, imag=True)
     psi = O.evolve(prep, W.gaussian_state(cfg.n, cfg.d, cfg.trap), prep_steps)
     p = O.Params.from_config(cfg, imag=False)
     o0 = obs(p, psi)
     psi = O.evolve(p, psi, steps)
-    return {"config": "C2", "prep_imag_steps": prep_steps, "prep_gd": 15.0, "steps": steps,
+    return {"config": "quench_128cubed", "prep_imag_steps": prep_steps, "prep_gd": 15.0, "steps": steps,
             "observables_start": o0, "observables": obs(p, psi), "samples": samples(psi, 22)}
 
 
-def make_c4():
-    cfg = W.CONFIGS["C4"]
+def make_adjoint_96cubed():
+    cfg = W.CONFIGS["adjoint_96cubed"]
     prep_steps, steps = 500, cfg.steps
     prep = O.Params.from_config(cfg, imag=True)
     psi0 = O.evolve(prep, W.gaussian_state(cfg.n, cfg.d, cfg.trap), prep_steps)
@@ -86,7 +86,7 @@ def make_c4():
     amp = knot_amplitudes(knots, steps, cfg.dt)
     p = O.Params.from_config(cfg, imag=False)
     J, psiN, dJ_da, dJ_dt, lam0 = O.adjoint_evolve(p, psi0, amp)
-    return {"config": "C4", "prep_imag_steps": prep_steps, "steps": steps, "knots": knots.tolist(),
+    return {"config": "adjoint_96cubed", "prep_imag_steps": prep_steps, "steps": steps, "knots": knots.tolist(),
             "amp": amp.tolist(), "J": J, "dJ_damp": dJ_da.tolist(), "dJ_dtrap": dJ_dt.tolist(),
             "samples_psiN": samples(psiN, 44), "samples_lam0": samples(lam0, 45)}
 
@@ -94,7 +94,8 @@ def make_c4():
 def main():
     which = sys.argv[1]
     t = time.time()
-    rec = {"c3": make_c3, "c2": make_c2, "c4": make_c4}[which]()
+    rec = {"imag_256cubed": make_imag_256cubed, "quench_128cubed": make_quench_128cubed,
+           "adjoint_96cubed": make_adjoint_96cubed}[which]()
     rec["oracle_seconds"] = round(time.time() - t, 1)
     with open(os.path.join(HERE, f"{which}_oracle.json"), "w") as f:
         json.dump(rec, f)

@@ -1,4 +1,4 @@
-"""Writes tests/golden/c1_oracle.json: the FP64 oracle's observables for the
+"""Writes tests/golden/imag_32cubed_oracle.json: the FP64 oracle's observables for the
 32^3 imaginary-time workload (isotropic trap, g = 20, gd = 5, R = 4, dt = 0.005,
 200 steps from the seeded noisy Gaussian).  Calls only the oracle and the seeded
 input module; the paper prints no such values, so this fixture is a regression
@@ -15,13 +15,13 @@ import workloads as W  # noqa: E402
 
 
 def main():
-    cfg = W.CONFIGS["C1"]
+    cfg = W.CONFIGS["imag_32cubed"]
     p = O.Params.from_config(cfg)
     psi = O.evolve(p, W.noisy_gaussian(cfg), cfg.steps)
     o = O.observables(p, psi)
     o["rms"] = [float(v) for v in o["rms"]]
-    out = {"workload": "32^3 imaginary time, 200 steps", "config": "C1", "observables": o}
-    with open(os.path.join(os.path.dirname(__file__), "c1_oracle.json"), "w") as f:
+    out = {"workload": "32^3 imaginary time, 200 steps", "config": "imag_32cubed", "observables": o}
+    with open(os.path.join(os.path.dirname(__file__), "imag_32cubed_oracle.json"), "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
 
 

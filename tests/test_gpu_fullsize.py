@@ -48,12 +48,12 @@ def _dtype(torch, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_c3_256cubed_imaginary_time(env, prec):
+def test_imag_256cubed_matches_oracle_record(env, prec):
     """256^3 imaginary time, 20 steps (the benchmark's plan shape)."""
     torch, dg = env
-    cfg = W.CONFIGS["C3"]
-    gold = _golden("c3")
-    _say(f"C3 {prec}: preparing")
+    cfg = W.CONFIGS["imag_256cubed"]
+    gold = _golden("imag_256cubed")
+    _say(f"imag_256cubed {prec}: preparing")
     plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, dtype=_dtype(torch, prec))
     psi = plan.new_state(W.noisy_gaussian(cfg))
     plan.step(psi, gold["steps"])
@@ -62,7 +62,7 @@ def test_c3_256cubed_imaginary_time(env, prec):
     g = gold["observables"]
     emu = abs(o["mu"] - g["mu"]) / abs(g["mu"])
     een = abs(o["energy"] - g["energy"]) / abs(g["energy"])
-    _say(f"C3 {prec}: sampled state err {err:.3e}, mu rel err {emu:.3e}, energy rel err {een:.3e}")
+    _say(f"imag_256cubed {prec}: sampled state err {err:.3e}, mu rel err {emu:.3e}, energy rel err {een:.3e}")
     tol = 1e-12 if prec == "f64" else 1e-5
     assert err < tol
     assert emu < tol and een < tol
@@ -70,12 +70,12 @@ def test_c3_256cubed_imaginary_time(env, prec):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_c2_128cubed_quench_real_time(env, prec):
+def test_quench_128cubed_real_time_matches_oracle_record(env, prec):
     """128^3: 200 imaginary-time steps at gd = 15, quench to gd = 20, 1000
     real-time steps; norm conservation and energy drift per dtype."""
     torch, dg = env
-    cfg = W.CONFIGS["C2"]
-    gold = _golden("c2")
+    cfg = W.CONFIGS["quench_128cubed"]
+    gold = _golden("quench_128cubed")
     plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, gold["prep_gd"], dtype=_dtype(torch, prec))
     psi = plan.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
     plan.step(psi, gold["prep_imag_steps"])
@@ -88,7 +88,7 @@ def test_c2_128cubed_quench_real_time(env, prec):
     g0, g1 = gold["observables_start"], gold["observables"]
     drift = o1["energy"] - o0["energy"]
     gdrift = g1["energy"] - g0["energy"]
-    _say(f"C2 {prec}: sampled state err {err:.3e}; norm drift {o1['norm'] - o0['norm']:.3e}; "
+    _say(f"quench_128cubed {prec}: sampled state err {err:.3e}; norm drift {o1['norm'] - o0['norm']:.3e}; "
          f"energy {o0['energy']:.12f} -> {o1['energy']:.12f} (drift {drift:.3e}, oracle {gdrift:.3e})")
     assert abs(o0["energy"] - g0["energy"]) < (1e-11 if prec == "f64" else 1e-5) * abs(g0["energy"])
     if prec == "f64":
@@ -101,8 +101,8 @@ def test_c2_128cubed_quench_real_time(env, prec):
         assert abs(drift - gdrift) < 1e-5 * abs(g0["energy"])
 
 
-def _c4_setup(torch, dg, prec, gold):
-    cfg = W.CONFIGS["C4"]
+def _adjoint_setup(torch, dg, prec, gold):
+    cfg = W.CONFIGS["adjoint_96cubed"]
     prep = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, dtype=_dtype(torch, prec))
     psi0 = prep.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
     prep.step(psi0, gold["prep_imag_steps"])
@@ -111,10 +111,10 @@ def _c4_setup(torch, dg, prec, gold):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
-def test_c4_adjoint_matches_oracle(env, prec):
+def test_adjoint_96cubed_matches_oracle_record(env, prec):
     torch, dg = env
-    gold = _golden("c4")
-    cfg, plan, psi0 = _c4_setup(torch, dg, prec, gold)
+    gold = _golden("adjoint_96cubed")
+    cfg, plan, psi0 = _adjoint_setup(torch, dg, prec, gold)
     W_ = dg.knot_matrix(len(gold["knots"]), gold["steps"], cfg.dt)
     amp = W_ @ np.asarray(gold["knots"])
     assert np.max(np.abs(amp - np.asarray(gold["amp"]))) < 1e-14
@@ -125,19 +125,19 @@ def test_c4_adjoint_matches_oracle(env, prec):
     e_t = np.max(np.abs(out["dJ_dtrap"] - np.asarray(gold["dJ_dtrap"]))) / np.max(np.abs(gold["dJ_dtrap"]))
     e_psi = _sample_err(out["psi_final"], gold["samples_psiN"])
     e_lam = _sample_err(out["dJ_dpsi0"], gold["samples_lam0"])
-    _say(f"C4 adjoint {prec}: J {e_J:.2e}, dJ/da {e_a:.2e}, dJ/dtrap {e_t:.2e}, psi_N {e_psi:.2e}, lam0 {e_lam:.2e}")
+    _say(f"adjoint_96cubed {prec}: J {e_J:.2e}, dJ/da {e_a:.2e}, dJ/dtrap {e_t:.2e}, psi_N {e_psi:.2e}, lam0 {e_lam:.2e}")
     tol = 1e-9 if prec == "f64" else 2e-3
     assert e_J < tol and e_a < tol and e_t < tol and e_lam < tol
     assert e_psi < (1e-11 if prec == "f64" else 1e-4)
 
 
-def test_c4_adjoint_against_finite_differences(env):
+def test_adjoint_96cubed_against_finite_differences(env):
     """Knot and (lambda, gamma) gradients through DgpeEvolve (FP64) against
     central differences h = 1e-4 of the GPU forward run: max |g - fd| /
     max |fd| <= 1e-4."""
     torch, dg = env
-    gold = _golden("c4")
-    cfg, plan, psi0 = _c4_setup(torch, dg, "f64", gold)
+    gold = _golden("adjoint_96cubed")
+    cfg, plan, psi0 = _adjoint_setup(torch, dg, "f64", gold)
     nsteps = gold["steps"]
     knots = torch.tensor(gold["knots"], dtype=torch.float64, requires_grad=True)
     lg = torch.tensor([cfg.trap[1], cfg.trap[2]], dtype=torch.float64, requires_grad=True)
@@ -167,6 +167,6 @@ def test_c4_adjoint_against_finite_differences(env):
     fdg = (forward(k0, cfg.trap[1], cfg.trap[2] + h) - forward(k0, cfg.trap[1], cfg.trap[2] - h)) / (2 * h)
     ek = np.max(np.abs(gk - fd)) / np.max(np.abs(fd))
     et = max(abs(gt[0] - fdl) / abs(fdl), abs(gt[1] - fdg) / abs(fdg))
-    _say(f"C4 FD check: knots {ek:.2e}, (lambda, gamma) {et:.2e}; |dJ/dknots| max {np.max(np.abs(fd)):.3e}")
+    _say(f"adjoint_96cubed FD check: knots {ek:.2e}, (lambda, gamma) {et:.2e}; |dJ/dknots| max {np.max(np.abs(fd)):.3e}")
     assert abs(float(J) - gold["J"]) < 1e-9 * abs(gold["J"])
     assert ek < 1e-4 and et < 1e-4

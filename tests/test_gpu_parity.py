@@ -139,7 +139,7 @@ def test_observables_match_oracle(dg, torch_mod, prec):
 def test_c1_workload_fp64(dg, torch_mod):
     """32^3 imaginary time, 200 steps: state within 1e-12 of the oracle and the
     observables against the stored oracle record."""
-    cfg = W.CONFIGS["C1"]
+    cfg = W.CONFIGS["imag_32cubed"]
     psi0 = W.noisy_gaussian(cfg)
     plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, cutoff=cfg.R, dtype=torch_mod.complex128)
     psi = plan.new_state(psi0)
@@ -147,10 +147,10 @@ def test_c1_workload_fp64(dg, torch_mod):
     got = psi.cpu().numpy()
     ref = O.evolve(O.Params.from_config(cfg), psi0, cfg.steps)
     err = _rel(got, ref)
-    _say(f"C1 200 steps rel L2 {err:.3e}")
+    _say(f"imag_32cubed 200 steps rel L2 {err:.3e}")
     assert err < 1e-12
     obs = plan.observables(psi)
-    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "c1_oracle.json")))["observables"]
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "imag_32cubed_oracle.json")))["observables"]
     for k in ("norm", "mu", "energy", "e_kin", "e_trap", "e_contact", "e_dd"):
         assert abs(obs[k] - gold[k]) <= 1e-11 * max(abs(gold[k]), 1e-3), k
     for i in range(4):
@@ -160,7 +160,7 @@ def test_c1_workload_fp64(dg, torch_mod):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_real_time_conserves_norm(dg, torch_mod, prec):
     n, d = (64, 64, 64), (0.2, 0.2, 0.2)
-    cfg = W.CONFIGS["C2"]
+    cfg = W.CONFIGS["quench_128cubed"]
     psi0 = W.gaussian_state(n, d, cfg.trap)
     plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=_dtype(torch_mod, prec))
     psi = plan.new_state(psi0)

@@ -67,22 +67,22 @@ class Config:
         return replace(self, **kw)
 
 
-# The five workloads of this project.  Parameters the paper does not state are
-# proposals; each is listed with its reading in the design doc.
+# The five workloads of this project, named by time mode and grid.  Parameters
+# the paper does not state are proposals (readings of the paper).
 CONFIGS = {
-    "C1": Config("C1", (32, 32, 32), (0.25, 0.25, 0.25), 0.005, (1.0, 1.0, 1.0),
+    "imag_32cubed": Config("imag_32cubed", (32, 32, 32), (0.25, 0.25, 0.25), 0.005, (1.0, 1.0, 1.0),
                  20.0, 5.0, True, 200, R=4.0, noise=1e-3, seed=1,
                  note="imaginary time, FP64, isotropic; mu, energy, rms"),
-    "C2": Config("C2", (128, 128, 128), (0.2, 0.2, 0.2), 0.002, (1.0, 1.0, 4.0),
+    "quench_128cubed": Config("quench_128cubed", (128, 128, 128), (0.2, 0.2, 0.2), 0.002, (1.0, 1.0, 4.0),
                  50.0, 20.0, False, 1000, seed=2,
                  note="real time after a quench gd 15 -> 20; norm and energy drift"),
-    "C3": Config("C3", (256, 256, 256), (0.1, 0.1, 0.1), 0.001, (1.0, 1.0, 0.5),
+    "imag_256cubed": Config("imag_256cubed", (256, 256, 256), (0.1, 0.1, 0.1), 0.001, (1.0, 1.0, 0.5),
                  100.0, 60.0, True, 1000, noise=1e-3, seed=3,
                  note="imaginary time at 256^3; the throughput workload"),
-    "C4": Config("C4", (96, 96, 96), (0.2, 0.2, 0.2), 0.002, (1.0, 1.0, 4.0),
+    "adjoint_96cubed": Config("adjoint_96cubed", (96, 96, 96), (0.2, 0.2, 0.2), 0.002, (1.0, 1.0, 4.0),
                  50.0, 15.0, False, 400, seed=4,
                  note="real time, adjoint of the final energy; 40 trap-amplitude knots"),
-    "C5": Config("C5", (512, 512, 256), (0.1, 0.1, 0.2), 0.001, (1.0, 1.0, 8.0),
+    "real_512x512x256": Config("real_512x512x256", (512, 512, 256), (0.1, 0.1, 0.2), 0.001, (1.0, 1.0, 8.0),
                  200.0, 150.0, False, 200, seed=5,
                  note="large anisotropic real-time grid, FP32"),
 }
