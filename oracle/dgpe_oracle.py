@@ -15,7 +15,7 @@ theorem ("Solution method"); the real-to-complex transform of the real density
 with its Hermitian half spectrum ("Summary of revisions", DBEC-GP-OMP package);
 row-major [x][y][z] storage with NX slowest (DBEC-GP-MPI package).  The paper
 prints no equations; the formulas below are the standard dimensionless dipolar
-GPE in trap units and are readings, each listed in the design doc:
+GPE in trap units and are readings of the paper where it is silent:
 
   i dpsi/dt = [-1/2 Lap + V + g |psi|^2 + gd Phi] psi     (real time)
     dpsi/dtau = -[...] psi                               (imaginary time)
