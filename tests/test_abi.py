@@ -90,3 +90,7 @@ def test_null_plan_calls_fail_cleanly(lib):
     lib.dgpe_plan_destroy(None)
     assert lib.dgpe_status_string(5) == b"DGPE_ENONFINITE"
     assert lib.dgpe_status_string(0) == b"DGPE_OK"
+
+
+def test_schedule_query_rejects_null_plan(lib):
+    assert lib.dgpe_plan_fused_y(None) == -1

@@ -146,3 +146,29 @@ def test_potential_is_linear_and_symmetric(env):
     p3 = plan.new_state(np.sqrt(n1 + 2 * n2))
     f3 = plan.potential(p3).cpu().numpy()
     assert np.max(np.abs(f3 - (f1 + 2 * f2))) < 1e-13 * np.max(np.abs(f3))
+
+
+def test_fused_y_schedule_follows_the_plan(env):
+    """dgpe_plan_fused_y reports the schedule dgpe_step runs: the fused y
+    schedule for imaginary-time plans whose grid has it (both precisions), the
+    separate y sweep in real time, with DGPE_PARAM_FUSED_Y = 0, without the
+    compiled passes, or for a grid with no compiled fused z pass; and
+    switching back to imaginary time restores it."""
+    torch, dg = env
+    d = (0.4, 0.3, 0.2)
+    for dtype in (torch.complex64, torch.complex128):
+        p = dg.Plan((16, 64, 256), d, 0.002, (1, 1, 1), 10.0, 4.0, dtype=dtype)
+        assert p.fused_y
+        p.set("real_time", 1)
+        assert not p.fused_y
+        p.set("real_time", 0)
+        assert p.fused_y
+        p.set("fused_y", 0)
+        assert not p.fused_y
+        p.set("fused_y", 1)
+        p.set("fast_fft", 0)
+        assert not p.fused_y
+        p.close()
+    q = dg.Plan((16, 24, 32), (0.4, 0.35, 0.3), 0.002, (1, 1, 1), 10.0, 4.0, dtype=torch.complex64)
+    assert not q.fused_y  # no compiled fused z pass for this grid
+    q.close()
