@@ -566,8 +566,8 @@ hipError_t launch_cn_ycarry(const Plan& p, void* car) {
                        (cx<T>*)car, p.n[0], p.n[1], p.n[2], ytab, lzb)
     if (K <= 4) DGPE_YC(4);
     else if (K <= 8) DGPE_YC(8);
-    else if (p.n[2] % 32)
-        DGPE_YC(16);
+    else if (p.n[2] % 32)  // the two-lane kernel takes 32 whole z columns per block
+        return hipErrorInvalidValue;
     else  // two lanes per column
         hipLaunchKernelGGL((k_cn_ycarry2<T, true, 8>), dim3((p.n[0] * p.n[2] + 31) / 32), dim3(64), 0,
                            p.stream, (cx<T>*)car, p.n[0], p.n[1], p.n[2], ytab, lzb);
