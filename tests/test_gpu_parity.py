@@ -274,3 +274,23 @@ def test_fused_y_schedule_matches_oracle(dg, torch_mod, shape, prec):
     e_f, e_s, e_fs = _rel(outs[0], ref), _rel(outs[1], ref), _rel(outs[0], outs[1])
     _say(f"  fused {e_f:.2e} separate {e_s:.2e} fused-vs-separate {e_fs:.2e}")
     assert max(e_f, e_s, e_fs) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_fused_y_single_step_calls_match_oracle(dg, torch_mod, prec):
+    """Five one-step calls of the fused y schedule (each ends with its own norm
+    reduction and rescale; no step hands sigma to the next) match five oracle
+    steps."""
+    n, d = (16, 64, 256), (0.4, 0.3, 0.1)
+    cfg = W.Config("t", n, d, 0.003, (1.0, 1.1, 0.8), 30.0, 12.0, True, 5, noise=1e-3, seed=13)
+    psi0 = W.noisy_gaussian(cfg)
+    plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=_dtype(torch_mod, prec))
+    assert plan.fused_y
+    psi = plan.new_state(psi0)
+    for _ in range(cfg.steps):
+        plan.step(psi, 1)
+    got = psi.cpu().numpy().astype(np.complex128)
+    ref = O.evolve(O.Params.from_config(cfg), psi0, cfg.steps)
+    err = _rel(got, ref)
+    _say(f"  single-step calls {prec}: rel L2 {err:.3e}")
+    assert err < TOL[prec]
