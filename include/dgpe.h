@@ -89,8 +89,9 @@ typedef enum {
 #define DGPE_OBJ_ENERGY 0
 #define DGPE_OBJ_OVERLAP 1
 
-/* Observables (paper: the programs report the chemical potential, energy and
- * rms sizes of the state).  Sums are FP64 over the grid times dV:
+/* Observables: the diagnostics this library evaluates after a run of steps
+ * (its own choice of reported quantities; the paper prints no formulas for
+ * them).  Sums are FP64 over the grid times dV:
  *   e_kin  = 1/2 sum_axes sum_{i=-1}^{N-1} |psi_{i+1} - psi_i|^2 / d^2 (ghost zeros)
  *   e_trap = sum a V0 |psi|^2,  e_contact = g/2 sum |psi|^4,  e_dd = gd/2 sum Phi |psi|^2
  *   energy = (e_kin + e_trap + e_contact + e_dd)/norm

@@ -192,6 +192,8 @@ class Plan:
         amp_p = None
         if amp is not None:
             a = np.ascontiguousarray(np.asarray(amp, dtype=np.float64))
+            if a.shape != (nsteps,):
+                raise ValueError("amp must have nsteps entries")
             amp_p = a.ctypes.data_as(_lib.P_double)
         ms = np.zeros(_lib.NPASS)
         tot = ctypes.c_double()
@@ -251,9 +253,16 @@ class DgpeEvolve:
                         raise DgpeError(6, "DgpeEvolve needs a real-time plan")
                     W = knot_matrix(knots.numel(), nsteps, plan.dt)
                     amp = W @ knots.detach().cpu().numpy().astype(np.float64)
-                    plan.set("lambda", float(lam_gam[0]))
-                    plan.set("gamma", float(lam_gam[1]))
-                    out = plan.adjoint(psi0.detach(), amp, ckpt_every, objective, target)
+                    # the trap (lambda, gamma) of this evaluation; the plan's own
+                    # values are restored afterwards, also when the call fails
+                    saved = (plan.trap[1], plan.trap[2])
+                    try:
+                        plan.set("lambda", float(lam_gam[0]))
+                        plan.set("gamma", float(lam_gam[1]))
+                        out = plan.adjoint(psi0.detach(), amp, ckpt_every, objective, target)
+                    finally:
+                        plan.set("lambda", saved[0])
+                        plan.set("gamma", saved[1])
                     ctx.gk = torch.from_numpy(W.T @ out["dJ_damp"])
                     ctx.gt = torch.from_numpy(out["dJ_dtrap"][1:3].copy())
                     ctx.gpsi = out["dJ_dpsi0"]

@@ -294,7 +294,10 @@ struct PassTimer {
         hipEvent_t a, b;
         hipError_t e = hipEventCreate(&a);
         if (e != hipSuccess) return e;
-        if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+        if ((e = hipEventCreate(&b)) != hipSuccess) {
+            hipEventDestroy(a);
+            return e;
+        }
         ev.push_back(a);
         ev.push_back(b);
         kind.push_back(k);
@@ -820,21 +823,23 @@ dgpe_status dgpe_step_profiled(dgpe_plan plan, void* psi, int32_t nsteps, const 
     dgpe_status st = check_ptr(psi, "psi");
     if (st != DGPE_OK) return st;
     if (nsteps < 0) return fail(DGPE_EINVAL, "nsteps must be >= 0");
+    if (amp)
+        for (int i = 0; i < nsteps; ++i)
+            if (!std::isfinite(amp[i])) return fail(DGPE_EINVAL, "amp must be finite");
     Plan& p = *plan;
-    PassTimer tm;
+    PassTimer tm;  // owns every event it records, including the call's own pair
     tm.on = true;
     tm.stream = p.stream;
-    hipEvent_t t0, t1;
-    DGPE_HIP(hipEventCreate(&t0));
-    DGPE_HIP(hipEventCreate(&t1));
-    DGPE_HIP(hipEventRecord(t0, p.stream));
+    DGPE_HIP(tm.begin(-1));  // the whole call
+    const size_t whole = tm.ev.size() - 2;
     st = p.f32 ? run_steps<float>(p, psi, nsteps, amp, &tm) : run_steps<double>(p, psi, nsteps, amp, &tm);
     if (st != DGPE_OK) return st;
-    DGPE_HIP(hipEventRecord(t1, p.stream));
+    DGPE_HIP(hipEventRecord(tm.ev[whole + 1], p.stream));
     DGPE_HIP(hipStreamSynchronize(p.stream));
     double sum[DGPE_NPASS] = {0};
     int cnt[DGPE_NPASS] = {0};
     for (size_t i = 0; i < tm.kind.size(); ++i) {
+        if (tm.kind[i] < 0) continue;
         float m = 0.f;
         DGPE_HIP(hipEventElapsedTime(&m, tm.ev[2 * i], tm.ev[2 * i + 1]));
         sum[tm.kind[i]] += m;
@@ -843,11 +848,9 @@ dgpe_status dgpe_step_profiled(dgpe_plan plan, void* psi, int32_t nsteps, const 
     for (int k = 0; k < DGPE_NPASS; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
     if (total_ms) {
         float m = 0.f;
-        DGPE_HIP(hipEventElapsedTime(&m, t0, t1));
+        DGPE_HIP(hipEventElapsedTime(&m, tm.ev[whole], tm.ev[whole + 1]));
         *total_ms = m;
     }
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
     return DGPE_OK;
 }
 

@@ -121,6 +121,38 @@ def test_long_lines_match_oracle(dg, torch_mod, shape, real_time, prec):
     assert err < TOL[prec]
 
 
+LARGE_ANISO_SHAPES = [
+    # 512-point y rows (k_rows2 with the 32 x 16 split), the real-time fused z
+    # pass at Nz = 256, and the strided y sweep over 32 segments
+    ((16, 512, 256), (0.1, 0.1, 0.2)),
+    # the 512-point x pass (FP32: 8 adjacent columns per block, the 32 x 16
+    # split) and the strided x sweep over 32 segments
+    ((512, 16, 256), (0.1, 0.1, 0.2)),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", LARGE_ANISO_SHAPES, ids=lambda s: "x".join(map(str, s[0])))
+def test_large_anisotropic_kernels_match_oracle(dg, torch_mod, shape, prec):
+    """Real time with the parameters of the 512 x 512 x 256 workload (trap
+    (1, 1, 8), g = 200, gd = 150, dt = 0.001, spacings 0.1/0.1/0.2) on grids
+    that take exactly that workload's kernel instantiations along one long
+    axis each."""
+    n, d = shape
+    big = W.CONFIGS["real_512x512x256"]
+    cfg = W.Config("t", n, d, big.dt, big.trap, big.g, big.gd, False, 3, noise=1e-3, seed=15)
+    _say(f"large anisotropic kernels {n} real {prec}")
+    psi0 = W.noisy_gaussian(cfg)
+    plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=_dtype(torch_mod, prec))
+    psi = plan.new_state(psi0)
+    plan.step(psi, cfg.steps)
+    got = psi.cpu().numpy().astype(np.complex128)
+    ref = O.evolve(O.Params.from_config(cfg), psi0, cfg.steps)
+    err = _rel(got, ref)
+    _say(f"  rel L2 {err:.3e}")
+    assert err < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_observables_match_oracle(dg, torch_mod, prec):
     n, d = (32, 36, 48), (0.3, 0.3, 0.25)
@@ -248,6 +280,8 @@ FUSED_Y_SHAPES = [
     ((12, 256, 256), (0.5, 0.08, 0.1)),  # 16 segments, x lines shorter than a segment
     ((8, 16, 256), (0.5, 0.5, 0.1)),     # one segment: every carry is zero
     ((8, 144, 256), (0.5, 0.15, 0.1)),   # 9 segments: the carry chains split 5 + 4
+    ((256, 32, 64), (0.1, 0.3, 0.2)),    # x sweep over 16 segments with the y carries (as at 256^3)
+    ((64, 64, 64), (0.25, 0.25, 0.25)),  # 4 x segments, 4 y segments
 ]
 
 

@@ -80,6 +80,24 @@ def test_potential_matches_bruteforce_dft(n):
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("n", [(4, 6, 8), (6, 4, 5)])
+def test_potential_default_cutoff_is_half_the_shortest_box_side(n):
+    """With R left at its default (R <= 0), the potential equals the brute-force
+    convolution with R = min_i(N_i d_i)/2, the written reading of the default
+    cut-off.  On (4, 6, 8) the shortest side is x, on (6, 4, 5) it is y and z,
+    so a default taken from one fixed axis fails one of the two."""
+    d = (0.7, 0.5, 0.4)
+    R_ref = 0.5 * min(n[a] * d[a] for a in range(3))
+    rng = np.random.default_rng(12)
+    field = rng.uniform(0.0, 1.0, size=n)
+    got = O.dipolar_potential(_params(n, d, gd=1.0), field)
+    ref = _bruteforce_potential(n, d, R_ref, field)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    # and a different radius gives a measurably different potential
+    other = _bruteforce_potential(n, d, 0.5 * n[0] * d[0] * 1.5, field)
+    assert np.max(np.abs(other - ref)) > 1e-3 * np.max(np.abs(ref))
+
+
 def test_isotropic_density_has_zero_dipolar_energy():
     # A spherically symmetric density on a cubic grid: the angular factor
     # 3 kz^2/k^2 - 1 averages to zero over the x<->y<->z permutations of k.
