@@ -123,6 +123,29 @@ dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[
                              uint32_t mode, void* workspace, size_t workspace_bytes,
                              void* hip_stream);
 
+/* Largest workspace an allocation-free plan can use (64 MiB: grids up to
+ * 128^3 in FP64 and 192^3 in FP32). */
+#define DGPE_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * plan as dgpe_plan_create, with the library's own device scratch array as
+ * the workspace instead of a caller buffer.  The array is a static device
+ * array of DGPE_NOALLOC_MAX_BYTES, one per device, held until the process
+ * ends; this call allocates no device memory (only the plan's host metadata).
+ * Arguments as for dgpe_plan_create; the plan lives on the current device.
+ *   DGPE_EWORKSPACE if dgpe_workspace_bytes(n, mode) > DGPE_NOALLOC_MAX_BYTES.
+ * Every allocation-free plan on a device shares that device's one array and
+ * fills it with its tables: creating another one overwrites them, so every
+ * earlier allocation-free plan on the device is superseded and its calls then
+ * return DGPE_ESTATE (destroy it as usual).  No part of the array needs to
+ * start at zero (each call writes what it reads).  Calls on allocation-free
+ * plans of one device that overlap in time (other streams or threads) race
+ * on the array.  The adjoint's own workspace is still the caller's. */
+dgpe_status dgpe_plan_create_noalloc(dgpe_plan* out, const int32_t n[3], const double d[3],
+                                     double dt, const double trap[3], double g, double gd,
+                                     double cutoff_R, uint32_t mode, void* hip_stream);
+
 /* Change one parameter (DGPE_PARAM_*).  DT and REAL_TIME rebuild the Thomas
  * tables (synchronous); the others take effect at the next launch. */
 dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value);

@@ -44,10 +44,13 @@ class Plan:
     cutoff    dipolar cut-off radius (<= 0: min(N_i d_i)/2)
     real_time False: imaginary time (renormalised every step); True: real time
     dtype     torch.complex128 (FP64 path) or torch.complex64 (FP32 path)
+    noalloc   True: no workspace tensor; the plan uses the library's static
+              device scratch (dgpe_plan_create_noalloc, at most 64 MiB; a later
+              such plan on the same device supersedes this one)
     """
 
     def __init__(self, n, d, dt, trap, g, gd, cutoff=0.0, real_time=False, dtype=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, noalloc=False):
         torch = _torch()
         dtype = torch.complex128 if dtype is None else dtype
         if dtype not in (torch.complex128, torch.complex64):
@@ -70,16 +73,25 @@ class Plan:
         nbytes = int(self.lib.dgpe_workspace_bytes(n_arr, self.mode))
         if nbytes == 0:
             raise DgpeError(2, f"unsupported grid {self.n}")
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
         self.stream = stream
         handle = ctypes.c_void_p()
         d_arr = (ctypes.c_double * 3)(*self.d)
         t_arr = (ctypes.c_double * 3)(*self.trap)
-        check(self.lib.dgpe_plan_create(ctypes.byref(handle), n_arr, d_arr, self.dt, t_arr, self.g,
-                                        self.gd, float(cutoff), self.mode, _ptr(self.workspace),
-                                        nbytes, ctypes.c_void_p(stream.cuda_stream)))
+        self.noalloc = bool(noalloc)
+        if self.noalloc:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                check(self.lib.dgpe_plan_create_noalloc(
+                    ctypes.byref(handle), n_arr, d_arr, self.dt, t_arr, self.g, self.gd,
+                    float(cutoff), self.mode, ctypes.c_void_p(stream.cuda_stream)))
+        else:
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            check(self.lib.dgpe_plan_create(ctypes.byref(handle), n_arr, d_arr, self.dt, t_arr,
+                                            self.g, self.gd, float(cutoff), self.mode,
+                                            _ptr(self.workspace), nbytes,
+                                            ctypes.c_void_p(stream.cuda_stream)))
         self.handle = handle
 
     # -- helpers ------------------------------------------------------------

@@ -28,6 +28,7 @@ PARAM = {"g": 0, "gd": 1, "nu": 2, "lambda": 3, "gamma": 4, "dt": 5, "real_time"
          "fused_y": 8}
 OBJECTIVE = {"energy": 0, "overlap": 1}
 NPASS = 8
+NOALLOC_MAX_BYTES = 64 << 20  # DGPE_NOALLOC_MAX_BYTES
 PASS_NAMES = ["r2c_z", "fft_y", "fft_x_mul", "ifft_y", "c2r_z_nonlinear_cn_z", "cn_y", "cn_x", "norm_reduce"]
 
 
@@ -44,6 +45,9 @@ SIGNATURES = {
     "dgpe_plan_create": (c_int32, [ctypes.POINTER(c_void_p), P_int32, P_double, c_double, P_double,
                                    c_double, c_double, c_double, c_uint32, c_void_p, c_size_t,
                                    c_void_p]),
+    "dgpe_plan_create_noalloc": (c_int32, [ctypes.POINTER(c_void_p), P_int32, P_double, c_double,
+                                           P_double, c_double, c_double, c_double, c_uint32,
+                                           c_void_p]),
     "dgpe_plan_set": (c_int32, [c_void_p, c_int32, c_double]),
     "dgpe_plan_set_stream": (c_int32, [c_void_p, c_void_p]),
     "dgpe_plan_fused_y": (c_int32, [c_void_p]),

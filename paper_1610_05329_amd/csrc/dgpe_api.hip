@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +18,11 @@
 #include "dgpe_internal.h"
 
 using namespace dgpe;
+
+// Workspace of the allocation-free plans (dgpe_plan_create_noalloc): one array
+// per device, held until the process ends.  Host code never passes this name
+// to a kernel or a copy: it uses the device address from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[DGPE_NOALLOC_MAX_BYTES];
 
 // The opaque handle of the C ABI is the plan itself.
 struct dgpe_plan_s : public dgpe::Plan {};
@@ -295,7 +302,7 @@ struct PassTimer {
         hipError_t e = hipEventCreate(&a);
         if (e != hipSuccess) return e;
         if ((e = hipEventCreate(&b)) != hipSuccess) {
-            hipEventDestroy(a);
+            (void)hipEventDestroy(a);
             return e;
         }
         ev.push_back(a);
@@ -305,7 +312,7 @@ struct PassTimer {
     }
     hipError_t end() { return on ? hipEventRecord(ev.back(), stream) : hipSuccess; }
     ~PassTimer() {
-        for (hipEvent_t e : ev) hipEventDestroy(e);
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
 };
 
@@ -586,6 +593,124 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
     return DGPE_OK;
 }
 
+
+// ---- plan creation ---------------------------------------------------------
+
+dgpe_status check_plan_args(const int32_t n[3], const double d[3], double dt, const double trap[3],
+                            double g, double gd, double cutoff_R, uint32_t mode) {
+    if (!n || !d || !trap) return fail(DGPE_EINVAL, "n, d and trap must be non-NULL");
+    if (mode & ~(DGPE_REAL | DGPE_F32)) return fail(DGPE_EINVAL, "unknown mode bits");
+    for (int a = 0; a < 3; ++a)
+        if (!size_ok(n[a]))
+            return fail(DGPE_EUNSUPPORTED_SIZE,
+                        "grid size " + std::to_string(n[a]) +
+                            " must be even, of the form 2^a 3^b, and in [4, 1024]");
+    for (int a = 0; a < 3; ++a)
+        if (!(d[a] > 0) || !std::isfinite(d[a])) return fail(DGPE_EINVAL, "spacings must be finite and > 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(DGPE_EINVAL, "dt must be finite and > 0");
+    if (!finite3(trap) || !std::isfinite(g) || !std::isfinite(gd) || !std::isfinite(cutoff_R))
+        return fail(DGPE_EINVAL, "trap, g, gd and cutoff must be finite");
+    return DGPE_OK;
+}
+
+// Generation of the allocation-free scratch per device: each allocation-free
+// plan records the value its creation set; a later creation on the same
+// device overwrites the tables, and the older plan is then refused.
+constexpr int kMaxDevices = 64;
+std::atomic<uint64_t> g_scratch_gen[kMaxDevices];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each device
+
+dgpe_status create_plan(dgpe_plan* out, const int32_t n[3], const double d[3], double dt,
+                        const double trap[3], double g, double gd, double cutoff_R, uint32_t mode,
+                        void* workspace, size_t workspace_bytes, hipStream_t stream,
+                        bool static_ws) {
+    const bool f32 = (mode & DGPE_F32) != 0;
+    int nn[3] = {n[0], n[1], n[2]};
+    size_t offs[OFF_END + 1];
+    Launch lc;
+    if (!layout(nn, f32, offs, &lc, (mode & DGPE_REAL) == 0))
+        return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape fits this grid");
+    dgpe_status st = check_ptr(workspace, "workspace");
+    if (st != DGPE_OK) return fail(DGPE_EWORKSPACE, dgpe_last_error());
+    if (workspace_bytes < offs[OFF_END])
+        return fail(DGPE_EWORKSPACE, "workspace too small: need " + std::to_string(offs[OFF_END]) +
+                                         " bytes");
+    int dev = 0;
+    DGPE_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DGPE_EINVAL, "device index out of range");
+    dgpe_plan_s* p = new (std::nothrow) dgpe_plan_s();
+    if (!p) return fail(DGPE_EINVAL, "out of host memory");
+    for (int a = 0; a < 3; ++a) {
+        p->n[a] = n[a];
+        p->d[a] = d[a];
+        p->trap[a] = trap[a];
+    }
+    p->dt = dt;
+    p->g = g;
+    p->gd = gd;
+    p->R = cutoff_R > 0 ? cutoff_R : 0.5 * std::min({n[0] * d[0], n[1] * d[1], n[2] * d[2]});
+    p->imag = (mode & DGPE_REAL) == 0;
+    p->f32 = f32;
+    p->stream = stream;
+    p->lc = lc;
+    p->device = dev;
+    p->static_ws = static_ws;
+    p->ws_gen = static_ws ? g_scratch_gen[p->device].load() : 0;
+    char* ws = (char*)workspace;
+    p->ws = ws;
+    p->ws_bytes = workspace_bytes;
+    p->spec = ws + offs[OFF_SPEC];
+    p->phi = ws + offs[OFF_PHI];
+    p->ukern = ws + offs[OFF_UK];
+    p->tw[0] = ws + offs[OFF_TWX];
+    p->tw[1] = ws + offs[OFF_TWY];
+    p->tw[2] = ws + offs[OFF_TWZ];
+    p->twr2c = ws + offs[OFF_TWR];
+    for (int a = 0; a < 3; ++a)
+        for (int c = 0; c < 2; ++c) p->cntab[a][c] = ws + offs[OFF_CN0 + 2 * a + c];
+    p->red = (double*)(ws + offs[OFF_RED]);
+    p->scal = (double*)(ws + offs[OFF_SCAL]);
+    p->red_count = red_count_for(nn, lc);
+    p->fx = factor(n[0]);
+    p->fy = factor(n[1]);
+    p->fz = factor(n[2] / 2);
+    p->fast = true;
+    p->fuse_y = true;
+    st = f32 ? build_tables<float>(*p) : build_tables<double>(*p);
+    if (st != DGPE_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return DGPE_OK;
+}
+
+// A plan on the allocation-free scratch is usable until the next
+// allocation-free plan is created on its device.
+dgpe_status plan_live(const Plan& p) {
+    if (p.static_ws && g_scratch_gen[p.device].load() != p.ws_gen)
+        return fail(DGPE_ESTATE,
+                    "this allocation-free plan was superseded by a later one on the same device "
+                    "(they share one scratch array)");
+    return DGPE_OK;
+}
+
+// Device address of the scratch array on device dev, looked up once per
+// device with that device current (the host-side name is not a device address).
+dgpe_status scratch_for_device(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(DGPE_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        DGPE_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(DGPE_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DGPE_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -625,76 +750,37 @@ dgpe_status dgpe_plan_create(dgpe_plan* out, const int32_t n[3], const double d[
                              void* hip_stream) {
     if (!out) return fail(DGPE_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!n || !d || !trap) return fail(DGPE_EINVAL, "n, d and trap must be non-NULL");
-    if (mode & ~(DGPE_REAL | DGPE_F32)) return fail(DGPE_EINVAL, "unknown mode bits");
-    for (int a = 0; a < 3; ++a)
-        if (!size_ok(n[a]))
-            return fail(DGPE_EUNSUPPORTED_SIZE,
-                        "grid size " + std::to_string(n[a]) +
-                            " must be even, of the form 2^a 3^b, and in [4, 1024]");
-    for (int a = 0; a < 3; ++a)
-        if (!(d[a] > 0) || !std::isfinite(d[a])) return fail(DGPE_EINVAL, "spacings must be finite and > 0");
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(DGPE_EINVAL, "dt must be finite and > 0");
-    if (!finite3(trap) || !std::isfinite(g) || !std::isfinite(gd) || !std::isfinite(cutoff_R))
-        return fail(DGPE_EINVAL, "trap, g, gd and cutoff must be finite");
-    const bool f32 = (mode & DGPE_F32) != 0;
-    int nn[3] = {n[0], n[1], n[2]};
-    size_t offs[OFF_END + 1];
-    Launch lc;
-    if (!layout(nn, f32, offs, &lc, (mode & DGPE_REAL) == 0))
-        return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape fits this grid");
-    dgpe_status st = check_ptr(workspace, "workspace");
-    if (st != DGPE_OK) return fail(DGPE_EWORKSPACE, dgpe_last_error());
-    if (workspace_bytes < offs[OFF_END])
-        return fail(DGPE_EWORKSPACE, "workspace too small: need " + std::to_string(offs[OFF_END]) +
-                                         " bytes");
-    dgpe_plan_s* p = new (std::nothrow) dgpe_plan_s();
-    if (!p) return fail(DGPE_EINVAL, "out of host memory");
-    for (int a = 0; a < 3; ++a) {
-        p->n[a] = n[a];
-        p->d[a] = d[a];
-        p->trap[a] = trap[a];
-    }
-    p->dt = dt;
-    p->g = g;
-    p->gd = gd;
-    p->R = cutoff_R > 0 ? cutoff_R : 0.5 * std::min({n[0] * d[0], n[1] * d[1], n[2] * d[2]});
-    p->imag = (mode & DGPE_REAL) == 0;
-    p->f32 = f32;
-    p->stream = (hipStream_t)hip_stream;
-    p->lc = lc;
-    hipGetDevice(&p->device);
-    char* ws = (char*)workspace;
-    p->ws = ws;
-    p->ws_bytes = workspace_bytes;
-    p->spec = ws + offs[OFF_SPEC];
-    p->phi = ws + offs[OFF_PHI];
-    p->ukern = ws + offs[OFF_UK];
-    p->tw[0] = ws + offs[OFF_TWX];
-    p->tw[1] = ws + offs[OFF_TWY];
-    p->tw[2] = ws + offs[OFF_TWZ];
-    p->twr2c = ws + offs[OFF_TWR];
-    for (int a = 0; a < 3; ++a)
-        for (int c = 0; c < 2; ++c) p->cntab[a][c] = ws + offs[OFF_CN0 + 2 * a + c];
-    p->red = (double*)(ws + offs[OFF_RED]);
-    p->scal = (double*)(ws + offs[OFF_SCAL]);
-    p->red_count = red_count_for(nn, lc);
-    p->fx = factor(n[0]);
-    p->fy = factor(n[1]);
-    p->fz = factor(n[2] / 2);
-    p->fast = true;
-    p->fuse_y = true;
-    st = f32 ? build_tables<float>(*p) : build_tables<double>(*p);
-    if (st != DGPE_OK) {
-        delete p;
-        return st;
-    }
-    *out = p;
-    return DGPE_OK;
+    dgpe_status st = check_plan_args(n, d, dt, trap, g, gd, cutoff_R, mode);
+    if (st != DGPE_OK) return st;
+    return create_plan(out, n, d, dt, trap, g, gd, cutoff_R, mode, workspace, workspace_bytes,
+                       (hipStream_t)hip_stream, false);
+}
+
+dgpe_status dgpe_plan_create_noalloc(dgpe_plan* out, const int32_t n[3], const double d[3],
+                                     double dt, const double trap[3], double g, double gd,
+                                     double cutoff_R, uint32_t mode, void* hip_stream) {
+    if (!out) return fail(DGPE_EINVAL, "out is NULL");
+    *out = nullptr;
+    dgpe_status st = check_plan_args(n, d, dt, trap, g, gd, cutoff_R, mode);
+    if (st != DGPE_OK) return st;
+    const size_t need = dgpe_workspace_bytes(n, mode);
+    if (need > DGPE_NOALLOC_MAX_BYTES)
+        return fail(DGPE_EWORKSPACE, "grid needs " + std::to_string(need) +
+                                         " bytes of workspace; the allocation-free plan holds at most " +
+                                         std::to_string((size_t)DGPE_NOALLOC_MAX_BYTES));
+    int dev = -1;
+    DGPE_HIP(hipGetDevice(&dev));
+    void* ws = nullptr;
+    if ((st = scratch_for_device(dev, &ws)) != DGPE_OK) return st;
+    // every plan created here before on this device is superseded from now on
+    g_scratch_gen[dev].fetch_add(1);
+    return create_plan(out, n, d, dt, trap, g, gd, cutoff_R, mode, ws, DGPE_NOALLOC_MAX_BYTES,
+                       (hipStream_t)hip_stream, true);
 }
 
 dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
     if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     if (!std::isfinite(value)) return fail(DGPE_EINVAL, "value must be finite");
     Plan& p = *plan;
     switch (param) {
@@ -743,6 +829,7 @@ int32_t dgpe_plan_fused_y(dgpe_plan plan) {
 
 dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp) {
     if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     dgpe_status st = check_ptr(psi, "psi");
     if (st != DGPE_OK) return st;
     if (nsteps < 0) return fail(DGPE_EINVAL, "nsteps must be >= 0");
@@ -755,6 +842,7 @@ dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* a
 
 dgpe_status dgpe_potential(dgpe_plan plan, const void* psi, void* phi) {
     if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     dgpe_status st = check_ptr(psi, "psi");
     if (st != DGPE_OK) return st;
     if ((st = check_ptr(phi, "phi")) != DGPE_OK) return st;
@@ -771,6 +859,7 @@ dgpe_status dgpe_potential(dgpe_plan plan, const void* psi, void* phi) {
 
 dgpe_status dgpe_energy_mu_rms(dgpe_plan plan, const void* psi, double amp, dgpe_obs* out) {
     if (!plan || !out) return fail(DGPE_EINVAL, "plan and out must be non-NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     dgpe_status st = check_ptr(psi, "psi");
     if (st != DGPE_OK) return st;
     if (!std::isfinite(amp)) return fail(DGPE_EINVAL, "amp must be finite");
@@ -788,6 +877,7 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
                               void* adj_ws, size_t adj_ws_bytes, void* psi_final, double* J,
                               double* dJ_damp, double dJ_dtrap[3], void* dJ_dpsi0) {
     if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     Plan& p = *plan;
     if (p.imag) return fail(DGPE_ESTATE, "the adjoint needs a real-time plan");
     if (nsteps < 1 || ckpt_every < 1) return fail(DGPE_EINVAL, "nsteps and ckpt_every must be >= 1");
@@ -820,6 +910,7 @@ dgpe_status dgpe_pass_bytes(dgpe_plan plan, double bytes[DGPE_NPASS]) {
 dgpe_status dgpe_step_profiled(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp,
                                double ms[DGPE_NPASS], double* total_ms) {
     if (!plan || !ms) return fail(DGPE_EINVAL, "plan and ms must be non-NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     dgpe_status st = check_ptr(psi, "psi");
     if (st != DGPE_OK) return st;
     if (nsteps < 0) return fail(DGPE_EINVAL, "nsteps must be >= 0");

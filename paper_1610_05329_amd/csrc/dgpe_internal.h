@@ -66,6 +66,8 @@ struct Plan {
     Launch lc;
     bool fast;  // use the two-factor register FFT passes where compiled
     bool fuse_y;  // let the fused z pass start the y solve where it can
+    bool static_ws;   // the workspace is the library's allocation-free scratch array
+    uint64_t ws_gen;  // that array's generation when this plan was created
 };
 
 size_t workspace_layout(const int n[3], bool f32, size_t* offs /* [16] or null */);

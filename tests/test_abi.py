@@ -94,3 +94,30 @@ def test_null_plan_calls_fail_cleanly(lib):
 
 def test_schedule_query_rejects_null_plan(lib):
     assert lib.dgpe_plan_fused_y(None) == -1
+
+
+def test_noalloc_plan_rejects_grids_beyond_its_scratch_before_device_work(lib):
+    """The allocation-free plan checks its arguments and the 64 MiB limit of its
+    static scratch before any HIP call (so this runs without a GPU)."""
+    def create(n, mode=0, dt=0.005):
+        h = ctypes.c_void_p()
+        st = lib.dgpe_plan_create_noalloc(ctypes.byref(h), _n(*n), (ctypes.c_double * 3)(0.2, 0.2, 0.2),
+                                          dt, (ctypes.c_double * 3)(1.0, 1.0, 1.0), 1.0, 1.0, 0.0,
+                                          mode, None)
+        return st, h
+    assert _lib.NOALLOC_MAX_BYTES == 64 << 20
+    # 192^3 FP64 needs about 116 MiB; 256^3 FP32 about 137 MiB
+    for n, mode in [((192, 192, 192), 0), ((256, 256, 256), 2)]:
+        assert lib.dgpe_workspace_bytes(_n(*n), mode) > _lib.NOALLOC_MAX_BYTES
+        st, h = create(n, mode)
+        assert st == 3 and not h.value
+        assert b"at most" in lib.dgpe_last_error()
+    assert create((30, 32, 32))[0] == 2
+    assert create((32, 32, 32), dt=-1.0)[0] == 1
+    h = ctypes.c_void_p()
+    assert lib.dgpe_plan_create_noalloc(None, _n(32, 32, 32), (ctypes.c_double * 3)(0.2, 0.2, 0.2),
+                                        0.005, (ctypes.c_double * 3)(1.0, 1.0, 1.0), 1.0, 1.0,
+                                        0.0, 0, None) == 1
+    # the largest grids it serves fit the limit
+    assert lib.dgpe_workspace_bytes(_n(128, 128, 128), 0) <= _lib.NOALLOC_MAX_BYTES
+    assert lib.dgpe_workspace_bytes(_n(192, 192, 192), 2) <= _lib.NOALLOC_MAX_BYTES
