@@ -32,16 +32,24 @@ One step n -> n+1 (first-order Lie splitting, nonlinear part first):
      Thomas elimination without pivoting.
   3. Imaginary time only: psi <- psi / sqrt(sum |psi|^2 dV).
 
+Variants of the same method (the paper's programs use the form above):
+  - the symmetric (Strang) step: nonlinear over dt/2, the three sweeps over dt,
+    nonlinear over dt/2 from the new density, then step 3;
+  - propagation to the ground state in imaginary time, stopped when the
+    chemical potential changes by less than a tolerance per step ("Solution
+    method": imaginary-time propagation to the stationary state).
+
 Parity pins (tests/test_oracle_pins.py): brute-force DFT convolution, radial
 quadrature of the cut-off kernel, the closed-form dipolar energy of an
 anisotropic Gaussian, dense linear solves, exact separable non-interacting
-evolution, the harmonic ground-state energy (1 + lam + gam)/2, norm
-conservation, time reversal, the virial theorem and finite differences of the
-adjoint.
+evolution (Lie and Strang), the harmonic ground-state energy (1 + lam + gam)/2,
+norm conservation, time reversal (and the exact symmetry of the Strang step),
+the second order in dt of the Strang step, the virial theorem and finite
+differences of the adjoint.
 """
 from __future__ import annotations
 
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -49,8 +57,8 @@ import numpy as np
 __all__ = [
     "Params", "grid", "trap_base", "cutoff_factor", "dipolar_kernel",
     "dipolar_potential", "cn_coefficient", "cn_solve_axis", "kinetic_step",
-    "nonlinear_step", "step", "evolve", "norm", "observables", "hamiltonian_apply",
-    "energy_total", "adjoint_evolve", "overlap_objective",
+    "nonlinear_step", "step", "strang_step", "evolve", "ground_state", "norm", "observables",
+    "hamiltonian_apply", "energy_total", "adjoint_evolve", "overlap_objective",
 ]
 
 
@@ -226,13 +234,62 @@ def step(p: Params, psi, a: float = 1.0, V0=None):
     return psi
 
 
-def evolve(p: Params, psi, nsteps: int, amp: Optional[Sequence[float]] = None):
-    """nsteps split steps; amp[n] is the trap amplitude a(t_n) of step n (1 if None)."""
+def strang_step(p: Params, psi, a: float = 1.0, V0=None):
+    """One symmetric (Strang) split step, the second-order variant of the same
+    splitting: the nonlinear step over dt/2 from the density of the incoming
+    state, the Crank-Nicolson sweeps over the full dt, the nonlinear step over
+    dt/2 from the density after the sweeps; then (imaginary time)
+    renormalisation to unit norm.  Both halves use the trap amplitude a of the
+    step."""
+    half = replace(p, dt=0.5 * p.dt)
+    psi = nonlinear_step(half, psi, a, V0)
+    psi = kinetic_step(p, psi)
+    psi = nonlinear_step(half, psi, a, V0)
+    if p.imag:
+        psi = psi / np.sqrt(norm(p, psi))
+    return psi
+
+
+SCHEMES = {"lie": step, "strang": strang_step}
+
+
+def evolve(p: Params, psi, nsteps: int, amp: Optional[Sequence[float]] = None,
+           scheme: str = "lie"):
+    """nsteps split steps; amp[n] is the trap amplitude a(t_n) of step n (1 if None).
+    scheme: "lie" (first order, the paper's form) or "strang" (second order)."""
+    one = SCHEMES[scheme]
     V0 = trap_base(p)
     psi = np.array(psi, dtype=np.complex128, copy=True)
     for n in range(nsteps):
-        psi = step(p, psi, 1.0 if amp is None else float(amp[n]), V0)
+        psi = one(p, psi, 1.0 if amp is None else float(amp[n]), V0)
     return psi
+
+
+def ground_state(p: Params, psi0, tol: float, max_steps: int, check_every: int = 1,
+                 scheme: str = "lie"):
+    """Imaginary-time propagation to the stationary state, stopped on the change
+    of the chemical potential.  mu is evaluated on psi0 and after every
+    check_every steps; the run stops at the first evaluation where
+    |mu_now - mu_before| / (steps between them) < tol, or after max_steps steps.
+
+    Returns (psi, steps done, the last |delta mu| per step, mu of psi)."""
+    assert p.imag and tol > 0 and max_steps >= 0 and check_every >= 1
+    one = SCHEMES[scheme]
+    V0 = trap_base(p)
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    mu = observables(p, psi)["mu"]
+    done, rate = 0, float("inf")
+    while done < max_steps:
+        k = min(check_every, max_steps - done)
+        for _ in range(k):
+            psi = one(p, psi, 1.0, V0)
+        done += k
+        mu_new = observables(p, psi)["mu"]
+        rate = abs(mu_new - mu) / k
+        mu = mu_new
+        if rate < tol:
+            break
+    return psi, done, rate, mu
 
 
 # ----------------------------------------------------------------------------

@@ -311,6 +311,130 @@ def test_interacting_ground_state_virial_and_eigen_residual():
 
 
 # ---------------------------------------------------------------------------
+# Strang splitting and the ground-state driver
+# ---------------------------------------------------------------------------
+
+def _axis_transfer_strang(p, axis, a=1.0):
+    """Dense one-axis transfer matrix of the symmetric step: half the trap phase,
+    the Crank-Nicolson solve, the other half of the trap phase."""
+    N = p.n[axis]
+    x = (np.arange(N) - N // 2) * p.d[axis]
+    v = 0.5 * (p.trap[axis] * x) ** 2
+    half = np.exp(-0.5 * p.dt * a * v) if p.imag else np.exp(-0.5j * p.dt * a * v)
+    A = p.dt / (4 * p.d[axis] ** 2) * (1.0 if p.imag else 1j)
+    D = -2 * np.eye(N) + np.eye(N, k=1) + np.eye(N, k=-1)
+    C = np.linalg.solve(np.eye(N) - A * D, np.eye(N) + A * D)
+    return np.diag(half) @ C @ np.diag(half)
+
+
+@pytest.mark.parametrize("imag", [False, True])
+def test_strang_noninteracting_step_is_exactly_separable(imag):
+    n, d = (10, 12, 14), (0.4, 0.3, 0.35)
+    p = _params(n, d, dt=0.02, trap=(1.0, 1.3, 2.1), imag=imag)
+    rng = np.random.default_rng(8)
+    f = [rng.normal(size=n[a]) + 1j * rng.normal(size=n[a]) for a in range(3)]
+    psi0 = np.einsum("i,j,k->ijk", *f)
+    steps = 15
+    got = O.evolve(p, psi0, steps, scheme="strang")
+    g = [np.linalg.matrix_power(_axis_transfer_strang(p, a), steps) @ f[a] for a in range(3)]
+    ref = np.einsum("i,j,k->ijk", *g)
+    if imag:
+        ref = ref / math.sqrt(np.sum(np.abs(ref) ** 2) * p.dV)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # and it differs from the first-order step by more than rounding
+    lie = O.evolve(p, psi0, steps)
+    assert np.max(np.abs(got - lie)) > 1e-6 * np.max(np.abs(ref))
+
+
+def _interacting_real(dt):
+    n, d = (16, 16, 16), (0.45, 0.45, 0.45)
+    return _params(n, d, dt=dt, trap=(1.0, 1.2, 1.6), g=25.0, gd=10.0)
+
+
+def test_strang_step_is_second_order_in_dt():
+    """At a fixed final time, halving dt shrinks the change of the final state
+    about fourfold for the symmetric step and about twofold for the
+    first-order one."""
+    psi0 = W.random_state((16, 16, 16), (0.45,) * 3, seed=17)
+    T = 0.08
+    ratios = {}
+    for scheme in ("strang", "lie"):
+        finals = []
+        for dt in (0.008, 0.004, 0.002):
+            p = _interacting_real(dt)
+            finals.append(O.evolve(p, psi0, int(round(T / dt)), scheme=scheme))
+        e1 = np.linalg.norm(finals[0] - finals[1])
+        e2 = np.linalg.norm(finals[1] - finals[2])
+        ratios[scheme] = e1 / e2
+    assert 3.6 < ratios["strang"] < 4.4, ratios
+    assert 1.6 < ratios["lie"] < 2.4, ratios
+
+
+def test_strang_real_time_step_is_its_own_reverse():
+    """S(-dt) S(dt) = 1: the symmetric step run backwards undoes itself (each
+    half phase sees the same density forwards and backwards, and the
+    Crank-Nicolson solve with -dt inverts the one with dt).  The first-order
+    step run backwards does not."""
+    p, back = _interacting_real(0.006), _interacting_real(-0.006)
+    psi0 = W.random_state(p.n, p.d, seed=18)
+    psi = O.evolve(p, psi0, 10, scheme="strang")
+    assert abs(O.norm(p, psi) - O.norm(p, psi0)) < 1e-13
+    again = O.evolve(back, psi, 10, scheme="strang")
+    assert np.max(np.abs(again - psi0)) < 1e-12 * np.max(np.abs(psi0))
+    lie_back = O.evolve(back, O.evolve(p, psi0, 10), 10)
+    assert np.max(np.abs(lie_back - psi0)) > 1e-6 * np.max(np.abs(psi0))
+
+
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+def test_ground_state_driver_reaches_the_noninteracting_fixed_point(scheme):
+    """Without interactions the stationary state of either step is the product
+    of the dominant eigenvectors of the one-axis transfer matrices; the driver
+    stops near it, on the first check whose mu change per step is below tol,
+    and its state is exactly that many plain steps from psi0."""
+    n, d = (24, 20, 28), (0.45, 0.5, 0.4)
+    p = _params(n, d, dt=0.02, trap=(1.0, 1.5, 2.0), imag=True)
+    psi0 = W.gaussian_state(n, d, (0.7, 1.0, 1.2))
+    tol, every = 1e-11, 7
+    psi, steps, rate, mu = O.ground_state(p, psi0, tol, 5000, every, scheme=scheme)
+    assert rate < tol and 0 < steps < 5000 and steps % every == 0
+    transfer = _axis_transfer_strang if scheme == "strang" else _axis_transfer
+    vecs = []
+    for a in range(3):
+        w, v = np.linalg.eig(transfer(p, a))
+        e = v[:, np.argmax(np.abs(w))]
+        vecs.append(e * np.sign(e[np.argmax(np.abs(e))].real))
+    ref = np.einsum("i,j,k->ijk", *vecs)
+    ref = ref / math.sqrt(O.norm(p, ref))
+    assert np.max(np.abs(psi - ref)) < 2e-5 * np.max(np.abs(ref))
+    assert abs(mu - O.observables(p, ref)["mu"]) < 1e-9
+    # the stopping rule: mu along the plain trajectory, one check at a time
+    traj = O.evolve(p, psi0, steps - every, scheme=scheme)
+    before = O.observables(p, traj)["mu"]
+    if steps > every:
+        older = O.observables(p, O.evolve(p, psi0, steps - 2 * every, scheme=scheme))["mu"]
+        assert abs(before - older) / every >= tol
+    np.testing.assert_array_equal(psi, O.evolve(p, traj, every, scheme=scheme))
+    assert abs(abs(mu - before) / every - rate) < 1e-15
+
+
+def test_ground_state_driver_interacting_virial():
+    # the dipolar ground state reached by the driver satisfies the virial
+    # theorem 2 E_kin - 2 E_trap + 3 E_c + 3 E_dd = 0 and H psi = mu psi
+    n, d = (24, 24, 24), (0.45, 0.45, 0.45)
+    p = _params(n, d, dt=0.004, trap=(1.0, 1.0, 1.4), g=20.0, gd=8.0, imag=True)
+    psi, steps, rate, mu = O.ground_state(p, W.gaussian_state(n, d, p.trap), 1e-9, 4000, 10,
+                                          scheme="strang")
+    assert rate < 1e-9 and steps < 4000
+    o = O.observables(p, psi)
+    assert o["mu"] == mu
+    scale = o["e_kin"] + o["e_trap"] + o["e_contact"] + abs(o["e_dd"])
+    vir = 2 * o["e_kin"] - 2 * o["e_trap"] + 3 * o["e_contact"] + 3 * o["e_dd"]
+    assert abs(vir) < 0.02 * scale
+    res = O.hamiltonian_apply(p, psi) - o["mu"] * psi
+    assert np.linalg.norm(res) < 0.01 * o["mu"] * np.linalg.norm(psi)
+
+
+# ---------------------------------------------------------------------------
 # Adjoint
 # ---------------------------------------------------------------------------
 
