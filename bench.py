@@ -9,16 +9,24 @@ Default run (one JSON line on stdout):
             steps, bracketed by device synchronisation (the paper's timing
             rule: only the iteration loop is timed, program summary, Testing
             results).
-  variants  the same workload in FP64, and the FP32 real-time adjoint
-            (forward, recompute and reverse sweeps, per forward step).
+  variants  the same workload in FP64; the same grid and parameters in real time
+            (FP32 and FP64); the FP32 real-time adjoint (forward, recompute
+            and reverse sweeps, per forward step); the 512 x 512 x 256 FP32
+            real-time workload.  Each with its fraction of the HBM peak on the
+            bytes its passes move and on the model bytes (22 s per point per
+            step, s = bytes per real; 82 s for the adjoint).
   roofline  per-pass HIP event timing of the dominant pass on the plan's
-            stream against its algorithmic HBM bytes; HBM traffic from the
-            committed rocprofv3 counter summary when it matches the sources.
-  cpu_baseline  the FP64 oracle on the host on a bounded sample (a few steps
-            of the same workload).
+            stream against its model HBM bytes (and the bytes it moves); HBM
+            traffic from the committed rocprofv3 counter summary when it
+            matches the sources.
+  cpu_baseline  the FP64 oracle on the host on a bounded sample (10 steps of
+            the same workload from the same state), with the host CPU model.
+  precision the FP32 and FP64 GPU states, mu and energy after those steps
+            against the oracle's, and FP32 against FP64.
 
 Other modes:
-  --profile-run        headline steps only (for rocprofv3 runs)
+  --profile-run        steps of one workload only (for rocprofv3 runs; --workload,
+                       --precision)
   --copy-calibration   a plain device copy of known size (counter calibration)
   --summarize DIR      turn rocprofv3 CSV output under DIR into profiles/ text
 """
@@ -104,7 +112,26 @@ def traffic_for(kernel, launches_per_step_of_kernel):
     return k["hbm_bytes_per_dispatch"]
 
 
+def host_cpu():
+    """Model name of the host CPU and the cores this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return model, avail
+
+
 def cpu_baseline(cfg, psi0, steps):
+    """The FP64 oracle as it stands, timed on the host for `steps` steps of the
+    workload; returns the record and the oracle's final state."""
     from oracle import dgpe_oracle as O
     p = O.Params.from_config(cfg)
     V0 = O.trap_base(p)
@@ -113,10 +140,73 @@ def cpu_baseline(cfg, psi0, steps):
     for _ in range(steps):
         psi = O.step(p, psi, 1.0, V0)
     dt = time.perf_counter() - t0
-    return {"value": cfg.npoints * steps / dt, "unit": "grid-point-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} FP64 oracle steps of the same {cfg.n[0]}^3 imaginary-time workload "
-                      f"({dt:.1f} s; numpy, single-threaded FFT and elementwise work)"}
+    model, avail = host_cpu()
+    rec = {"value": cfg.npoints * steps / dt, "unit": "grid-point-steps/s", "cores": 1,
+           "kind": "oracle", "cpu_model": model, "host_cores_available": avail,
+           "sample": f"{steps} FP64 oracle steps of the same {cfg.n[0]}^3 imaginary-time workload "
+                     f"from the same seeded state ({dt:.1f} s; numpy: pocketfft and the elementwise "
+                     f"and Thomas work run on one thread)"}
+    return rec, psi
+
+
+def oracle_observables(cfg, psi):
+    from oracle import dgpe_oracle as O
+    return O.observables(O.Params.from_config(cfg), psi)
+
+
+# Model HBM bytes per grid point per step of the seven-pass schedule (s = bytes
+# per real): P1 3s (read psi, write the half spectrum), P2, P3, P4 2s each (the
+# half spectrum in place), P5 5s (read spectrum and psi, write psi), P6 and P7
+# 4s each (psi in place): 22 s.  The adjoint (forward, recompute and reverse
+# sweeps) moves about 82 s per forward step.
+MODEL_S_PER_POINT = 22
+ADJOINT_MODEL_S_PER_POINT = 82
+
+
+def model_pass_bytes(n, s):
+    """Model bytes of one launch of each pass, for the separate y schedule
+    (the fused y schedule adds carry arrays to P5 and P7 and replaces P6)."""
+    nt = n[0] * n[1] * n[2]
+    state = 2.0 * s * nt
+    spec = 2.0 * s * n[0] * n[1] * (n[2] // 2 + 1)
+    uk = s * (n[0] // 2 + 1) * (n[1] // 2 + 1) * (n[2] // 2 + 1)
+    return {"r2c_z": state + spec, "fft_y": 2 * spec, "fft_x_mul": 2 * spec + uk, "ifft_y": 2 * spec,
+            "c2r_z_nonlinear_cn_z": spec + 2 * state, "cn_y": 2 * state, "cn_x": 2 * state}
+
+
+def frac(bytes_, seconds):
+    return round(bytes_ / seconds / 1e9 / HBM_PEAK_GBS, 4)
+
+
+def measure(torch, dg, cfg, real_time, dtype, steps, warmup, psi0=None, per_pass=True):
+    """Time `steps` plain steps of one workload; the step's rate, bytes moved
+    (the passes' own counts) and model bytes against the HBM peak, and the
+    per-pass event timing."""
+    import workloads as W
+    s = 4 if dtype == torch.complex64 else 8
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=real_time, dtype=dtype)
+    init = plan.new_state(W.noisy_gaussian(cfg) if psi0 is None else psi0)
+    psi = init.clone()
+    wall, _ = timed_steps(torch, plan, psi, init, steps, warmup)
+    assert torch.isfinite(torch.view_as_real(psi)).all().item(), "non-finite state"
+    moved = sum(plan.pass_bytes().values())
+    model = MODEL_S_PER_POINT * s * cfg.npoints
+    out = {"value": cfg.npoints * steps / wall, "ms_per_step": wall * 1e3 / steps, "steps": steps,
+           "grid": list(cfg.n), "time": "real" if real_time else "imaginary",
+           "dtype": "f32" if s == 4 else "f64", "fused_y": plan.fused_y,
+           "step_bytes_moved": moved, "step_frac_of_peak": frac(moved * steps, wall),
+           "step_model_bytes": model, "step_frac_of_peak_model_bytes": frac(model * steps, wall)}
+    if per_pass:
+        psi.copy_(init)
+        ms, _ = plan.step_profiled(psi, min(steps, CHUNK))
+        pb = plan.pass_bytes()
+        out["per_pass_ms"] = {k: round(v, 5) for k, v in ms.items() if v > 0}
+        out["per_pass_frac"] = {k: round(pb[k] / (v * 1e-3) / 1e9 / HBM_PEAK_GBS, 3)
+                                for k, v in ms.items() if v > 0 and pb[k] > 1e6}
+    plan.close()
+    del plan, psi, init
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -135,13 +225,17 @@ def main():
                          "(only for the workload of the JSON line)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=40)
-    ap.add_argument("--workload", choices=["imag_256cubed", "real_512x512x256", "adjoint_256cubed"],
+    ap.add_argument("--workload", choices=["imag_256cubed", "real_256cubed", "real_512x512x256",
+                                           "adjoint_256cubed"],
                     default="imag_256cubed",
                     help="workload of --profile-run (the JSON line always uses imag_256cubed); "
-                         "adjoint_256cubed = the FP32 real-time adjoint on that grid (--steps forward steps, "
+                         "real_256cubed = the same grid and parameters in real time; "
+                         "adjoint_256cubed = the real-time adjoint on that grid (--steps forward steps, "
                          "checkpoints every 10)")
+    ap.add_argument("--precision", choices=["f32", "f64"], default="f32",
+                    help="precision of --profile-run")
     args = ap.parse_args()
 
     if args.summarize:
@@ -174,10 +268,10 @@ def main():
         log(f"copy calibration: 5 copies of {n * 4} bytes")
         return
 
+    pdtype = torch.complex64 if args.precision == "f32" else torch.complex128
     if args.profile_run and args.workload == "adjoint_256cubed":
         cfg = W.CONFIGS["imag_256cubed"]
-        plan_a = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True,
-                         dtype=torch.complex64)
+        plan_a = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=pdtype)
         psia = plan_a.new_state(W.noisy_gaussian(cfg))
         amp = np.ones(args.steps + 1)
         plan_a.adjoint(psia, amp[:3], ckpt_every=2)  # warm-up
@@ -185,14 +279,14 @@ def main():
         torch.cuda.synchronize()
         log("[bench] adjoint profile run done")
         return
-    cfg = W.CONFIGS[args.workload if args.profile_run else "imag_256cubed"]
-    log(f"[bench] workload {cfg.n} {'imaginary' if cfg.imag else 'real'} time; preparing seeded state")
-    psi0 = W.noisy_gaussian(cfg)
-    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=not cfg.imag,
-                   dtype=torch.complex64)
-    psi_init = plan.new_state(psi0)
-    psi = psi_init.clone()
     if args.profile_run:
+        name = "imag_256cubed" if args.workload == "real_256cubed" else args.workload
+        cfg = W.CONFIGS[name]
+        real_time = not cfg.imag or args.workload == "real_256cubed"
+        log(f"[bench] profile run {args.workload} {args.precision}")
+        plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=real_time, dtype=pdtype)
+        psi_init = plan.new_state(W.noisy_gaussian(cfg))
+        psi = psi_init.clone()
         for k in (args.warmup, args.steps):
             psi.copy_(psi_init)
             plan.step(psi, min(k, CHUNK))
@@ -200,47 +294,64 @@ def main():
         log("[bench] profile run done")
         return
 
+    cfg = W.CONFIGS["imag_256cubed"]
+    log(f"[bench] workload {cfg.n} imaginary time; preparing seeded state")
+    psi0 = W.noisy_gaussian(cfg)
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False,
+                   dtype=torch.complex64)
+    psi_init = plan.new_state(psi0)
+    psi = psi_init.clone()
     wall, ev = timed_steps(torch, plan, psi, psi_init, args.steps, args.warmup)
     value = cfg.npoints * args.steps / wall
     log(f"[bench] FP32: {args.steps} steps in {wall * 1e3:.2f} ms wall ({ev * 1e3:.2f} ms events)")
     assert torch.isfinite(torch.view_as_real(psi)).all().item(), "non-finite state"
 
-    # roofline: per-pass events over a second timed region
+    # roofline: per-pass events (on the plan's stream) over a second timed region
     psi.copy_(psi_init)
     ms, tot = plan.step_profiled(psi, min(args.steps, CHUNK))
     pbytes = plan.pass_bytes()
+    mbytes = model_pass_bytes(cfg.n, 4)
     per_step_bytes = sum(pbytes.values())
+    step_model = MODEL_S_PER_POINT * 4 * cfg.npoints
     share = {k: v for k, v in ms.items() if v > 0}
     dom = max(share, key=share.get)  # longest average launch
     kernel_of = dict(KERNEL_OF_PASS, cn_y="k_cn_ycarry") if plan.fused_y else KERNEL_OF_PASS
-    ach = pbytes[dom] / (ms[dom] * 1e-3) / 1e9
+    ach = mbytes[dom] / (ms[dom] * 1e-3) / 1e9
+    ach_moved = pbytes[dom] / (ms[dom] * 1e-3) / 1e9
     roofline = {
         "bound": "hbm", "kernel": kernel_of[dom], "pass": dom, "fused_y": plan.fused_y,
         "achieved": round(ach, 1),
         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
         "traffic": traffic_for(kernel_of[dom], 1),
-        "avg_launch_ms": round(ms[dom], 5), "algorithmic_bytes_per_launch": pbytes[dom],
+        "avg_launch_ms": round(ms[dom], 5),
+        "algorithmic_bytes_per_launch": mbytes[dom],
+        "algorithmic_bytes_rule": "model bytes of the pass: 2s per half-spectrum value read, "
+                                  "2s per state point read and 2s written (s = 4)",
+        "bytes_moved_per_launch": pbytes[dom],
+        "achieved_on_bytes_moved": round(ach_moved, 1),
+        "frac_on_bytes_moved": round(ach_moved / HBM_PEAK_GBS, 4),
         "per_pass_ms": {k: round(v, 5) for k, v in ms.items()},
         "per_pass_GBs": {k: round(pbytes[k] / (ms[k] * 1e-3) / 1e9, 1) for k in share},
-        "step_algorithmic_bytes": per_step_bytes,
+        "step_bytes_moved": per_step_bytes,
         "step_effective_GBs": round(per_step_bytes * args.steps / wall / 1e9, 1),
         "step_frac_of_peak": round(per_step_bytes * args.steps / wall / 1e9 / HBM_PEAK_GBS, 4),
+        "step_model_bytes": step_model,
+        "step_frac_of_peak_model_bytes": frac(step_model * args.steps, wall),
     }
-    log(f"[bench] dominant pass {dom}: {ach:.0f} GB/s; step effective "
-        f"{roofline['step_effective_GBs']} GB/s")
+    log(f"[bench] dominant pass {dom}: {ach:.0f} GB/s on model bytes ({ach_moved:.0f} on bytes moved); "
+        f"step {roofline['step_effective_GBs']} GB/s moved")
+    plan.close()
+    del plan, psi, psi_init
+    torch.cuda.empty_cache()
 
     variants = {}
     if not args.no_variants:
-        plan64 = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=torch.complex128)
-        init64 = plan64.new_state(psi0)
-        psi64 = init64.clone()
-        w64, _ = timed_steps(torch, plan64, psi64, init64, args.steps, args.warmup)
-        b64 = sum(plan64.pass_bytes().values())
-        variants["f64"] = {"value": cfg.npoints * args.steps / w64, "ms_per_step": w64 * 1e3 / args.steps,
-                           "step_effective_GBs": round(b64 * args.steps / w64 / 1e9, 1)}
-        log(f"[bench] FP64: {w64 * 1e3 / args.steps:.3f} ms/step")
-        del plan64, psi64, init64
-        torch.cuda.empty_cache()
+        variants["f64"] = measure(torch, dg, cfg, False, torch.complex128, args.steps, args.warmup, psi0)
+        log(f"[bench] FP64 imaginary time: {variants['f64']['ms_per_step']:.3f} ms/step")
+        for prec, dt_ in (("f32", torch.complex64), ("f64", torch.complex128)):
+            k = f"real_256cubed_{prec}"
+            variants[k] = measure(torch, dg, cfg, True, dt_, 20, 5, psi0)
+            log(f"[bench] {prec} real time 256^3: {variants[k]['ms_per_step']:.3f} ms/step")
         # adjoint: real time, FP32, energy objective, checkpoints every 10 steps
         na = args.adjoint_steps
         plan_a = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=torch.complex64)
@@ -252,31 +363,64 @@ def main():
         out = plan_a.adjoint(psia, amp, ckpt_every=10)
         torch.cuda.synchronize()
         wa = time.perf_counter() - t0
+        amodel = ADJOINT_MODEL_S_PER_POINT * 4 * cfg.npoints
         variants["adjoint_f32"] = {"value": cfg.npoints * na / wa, "ms_per_step": wa * 1e3 / na,
                                    "steps": na, "ckpt_every": 10, "objective": "energy",
-                                   "J": out["J"]}
+                                   "J": out["J"], "step_model_bytes": amodel,
+                                   "step_frac_of_peak_model_bytes": frac(amodel * na, wa)}
         log(f"[bench] adjoint FP32: {wa * 1e3 / na:.3f} ms per forward step")
+        plan_a.close()
         del plan_a, psia, out
         torch.cuda.empty_cache()
         # 512 x 512 x 256 FP32 real time (the large anisotropic workload)
         big = W.CONFIGS["real_512x512x256"]
-        plan_big = dg.Plan(big.n, big.d, big.dt, big.trap, big.g, big.gd, real_time=True, dtype=torch.complex64)
-        init_big = plan_big.new_state(W.noisy_gaussian(big))
-        psi_big = init_big.clone()
-        n_big = 20
-        w_big, _ = timed_steps(torch, plan_big, psi_big, init_big, n_big, 5)
-        b_big = sum(plan_big.pass_bytes().values())
-        variants["real_512x512x256_f32"] = {
-            "value": big.npoints * n_big / w_big, "ms_per_step": w_big * 1e3 / n_big,
-            "grid": list(big.n), "step_effective_GBs": round(b_big * n_big / w_big / 1e9, 1)}
-        log(f"[bench] 512x512x256 FP32 real time: {w_big * 1e3 / n_big:.3f} ms/step")
-        del plan_big, psi_big, init_big
-        torch.cuda.empty_cache()
+        variants["real_512x512x256_f32"] = measure(torch, dg, big, True, torch.complex64, 20, 5)
+        log(f"[bench] 512x512x256 FP32 real time: "
+            f"{variants['real_512x512x256_f32']['ms_per_step']:.3f} ms/step")
 
     cpu = None
+    precision = None
     if not args.no_cpu_baseline:
-        log(f"[bench] CPU oracle baseline: {args.cpu_steps} steps")
-        cpu = cpu_baseline(cfg, psi0, args.cpu_steps)
+        k = args.cpu_steps
+        log(f"[bench] CPU oracle baseline: {k} steps")
+        cpu, psi_o = cpu_baseline(cfg, psi0, k)
+        # the precision form against the FP64 GPU run and the oracle, after the
+        # same k steps from the same state
+        obs_o = oracle_observables(cfg, psi_o)
+        gpu = {}
+        for prec, dt_ in (("f32", torch.complex64), ("f64", torch.complex128)):
+            pl = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=False, dtype=dt_)
+            st = pl.new_state(psi0)
+            pl.step(st, k)
+            gpu[prec] = (pl.observables(st), st.cpu().numpy().astype(np.complex128))
+            pl.close()
+            del pl, st
+        torch.cuda.empty_cache()
+
+        def rel(a, b):
+            return float(abs(a - b) / abs(b))
+
+        def l2(a, b):
+            return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        precision = {"steps": k, "workload": "imag_256cubed"}
+        for prec in ("f32", "f64"):
+            o, st = gpu[prec]
+            precision[prec] = {
+                "mu": o["mu"], "energy": o["energy"],
+                "mu_rel_err_vs_oracle": rel(o["mu"], obs_o["mu"]),
+                "energy_rel_err_vs_oracle": rel(o["energy"], obs_o["energy"]),
+                "psi_rel_l2_vs_oracle": l2(st, psi_o)}
+        o32, s32 = gpu["f32"]
+        o64, s64 = gpu["f64"]
+        precision["f32"].update({
+            "mu_rel_err_vs_f64_gpu": rel(o32["mu"], o64["mu"]),
+            "energy_rel_err_vs_f64_gpu": rel(o32["energy"], o64["energy"]),
+            "psi_rel_l2_vs_f64_gpu": l2(s32, s64)})
+        precision["oracle"] = {"mu": obs_o["mu"], "energy": obs_o["energy"]}
+        log(f"[bench] precision after {k} steps: FP32 mu {precision['f32']['mu_rel_err_vs_oracle']:.2e}, "
+            f"E {precision['f32']['energy_rel_err_vs_oracle']:.2e}, psi "
+            f"{precision['f32']['psi_rel_l2_vs_oracle']:.2e} vs the oracle; FP64 psi "
+            f"{precision['f64']['psi_rel_l2_vs_oracle']:.2e}")
 
     line = {
         "metric": "grid-point-steps/sec at 256^3 (FP32 plain imaginary-time step)",
@@ -284,7 +428,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded Gaussian + uniform noise, generated on the host)",
-        "config": workload(cfg), "roofline": roofline, "cpu_baseline": cpu, "variants": variants,
+        "config": workload(cfg), "roofline": roofline, "cpu_baseline": cpu, "precision": precision,
+        "variants": variants,
     }
     print(json.dumps(line), flush=True)
 

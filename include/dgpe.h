@@ -84,6 +84,8 @@ typedef enum {
 #define DGPE_PARAM_FUSED_Y 8   /* 1 (default): in imaginary time, the fused z pass also solves the y axis
                                   in 16-line segments and pass 5 joins them (see the pass list); 0: the
                                   separate y sweep.  Same result to rounding either way */
+#define DGPE_PARAM_SCHEME 9    /* 0 (default): the first-order (Lie) step of the paper's method;
+                                  1: the symmetric (Strang) step, see dgpe_step */
 
 /* adjoint objectives */
 #define DGPE_OBJ_ENERGY 0
@@ -161,13 +163,49 @@ int32_t dgpe_plan_fused_y(dgpe_plan plan);
 /* Advance psi (device, [Nx][Ny][Nz] complex of the plan precision, in place) by
  * nsteps split steps.  amp: host array of nsteps trap amplitudes a(t_n) (NULL:
  * all 1); it is read during the call only.  In imaginary time the returned
- * state has unit norm.  Asynchronous. */
+ * state has unit norm.  Asynchronous.
+ * With DGPE_PARAM_SCHEME = 1 each step is the symmetric (Strang) step: the
+ * nonlinear step over dt/2 from the incoming density, the three sweeps over
+ * dt, the nonlinear step over dt/2 from the density after the sweeps, then the
+ * renormalisation (imaginary time); both halves use a(t_n).  Second order in
+ * dt, against first order for the default step; the paper's programs use the
+ * default step.  The fused y schedule is not used with it. */
 dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* amp);
+
+/* Imaginary-time propagation to the stationary state (paper, "Solution
+ * method": propagation in imaginary time yields the ground state), stopped on
+ * the change of the chemical potential.  mu (as in dgpe_energy_mu_rms, trap
+ * amplitude 1) is evaluated on the incoming psi and after every check_every
+ * steps; the run stops at the first evaluation where
+ * |mu_now - mu_before| / (steps between them) < tol, or after max_steps steps.
+ *   psi           device state (in place); returned with unit norm
+ *   steps_done    steps taken; dmu_per_step: the last |delta mu| per step
+ *                 (+inf if no step ran); converged iff *dmu_per_step < tol
+ *   obs           observables of the returned state
+ * Imaginary-time plans only (DGPE_ESTATE otherwise).  Uses the plan's scheme.
+ * Synchronises the stream at every check. */
+dgpe_status dgpe_ground_state(dgpe_plan plan, void* psi, double tol, int32_t max_steps,
+                              int32_t check_every, int32_t* steps_done, double* dmu_per_step,
+                              dgpe_obs* obs);
 
 /* Dipolar potential Phi = IDFT[U_R DFT[|psi|^2]] of a state (paper, "Solution
  * method": the dipolar term through the convolution theorem).  phi: device
  * [Nx][Ny][Nz] real of the plan precision.  Asynchronous. */
 dgpe_status dgpe_potential(dgpe_plan plan, const void* psi, void* phi);
+
+/* Density |psi|^2 of a state (FP64 products rounded once): out is device
+ * [Nx][Ny][Nz] real of the plan precision.  Asynchronous. */
+dgpe_status dgpe_density(dgpe_plan plan, const void* psi, void* out);
+
+/* Write the density of psi to the file at path in binary form (paper,
+ * "Summary of revisions", MPI output format: binary density output into one
+ * file, each part at its offset): Nx*Ny*Nz IEEE float64 values in the host's
+ * byte order (little-endian here), row-major [x][y][z] with x slowest, no
+ * header; the part of x-planes [x0, x1) starts at byte 8*x0*Ny*Nz.  The
+ * density passes through the plan's workspace (its Phi buffer) and a bounded
+ * host buffer.  Synchronises the stream.  DGPE_EINVAL if the file cannot be
+ * written. */
+dgpe_status dgpe_write_density(dgpe_plan plan, const void* psi, const char* path);
 
 /* Norm, chemical potential, energy and its parts, rms sizes of psi with trap
  * amplitude amp.  Synchronises the stream; DGPE_ENONFINITE if any sum is not

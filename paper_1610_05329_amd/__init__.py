@@ -117,7 +117,9 @@ class Plan:
 
     def set(self, name, value):
         """Change one parameter: g, gd, nu, lambda, gamma, dt, real_time,
-        fast_fft (0/1) or fused_y (0/1)."""
+        fast_fft (0/1), fused_y (0/1) or scheme ("lie"/"strang" or 0/1)."""
+        if name == "scheme" and isinstance(value, str):
+            value = _lib.SCHEME[value]
         check(self.lib.dgpe_plan_set(self.handle, _lib.PARAM[name], float(value)))
         if name == "g":
             self.g = float(value)
@@ -144,6 +146,20 @@ class Plan:
         check(self.lib.dgpe_step(self.handle, _ptr(psi), int(nsteps), amp_p))
         return psi
 
+    def ground_state(self, psi, tol=1e-10, max_steps=20000, check_every=10):
+        """Imaginary-time steps on psi (in place) until mu changes by less than
+        tol per step between checks every check_every steps, or max_steps.
+        Returns dict(steps, dmu_per_step, converged, observables)."""
+        self._check_state(psi)
+        steps = ctypes.c_int32()
+        rate = ctypes.c_double()
+        o = _lib.DgpeObs()
+        check(self.lib.dgpe_ground_state(self.handle, _ptr(psi), float(tol), int(max_steps),
+                                         int(check_every), ctypes.byref(steps), ctypes.byref(rate),
+                                         ctypes.byref(o)))
+        return {"steps": steps.value, "dmu_per_step": rate.value, "converged": rate.value < tol,
+                "observables": _obs_dict(o)}
+
     def potential(self, psi, out=None):
         """Dipolar potential Phi of |psi|^2 on the grid (real, plan precision)."""
         torch = _torch()
@@ -153,14 +169,27 @@ class Plan:
         check(self.lib.dgpe_potential(self.handle, _ptr(psi), _ptr(out)))
         return out
 
+    def density(self, psi, out=None):
+        """|psi|^2 on the grid (real, plan precision)."""
+        torch = _torch()
+        self._check_state(psi)
+        if out is None:
+            out = torch.empty(self.n, dtype=self.rdtype, device=self.device)
+        check(self.lib.dgpe_density(self.handle, _ptr(psi), _ptr(out)))
+        return out
+
+    def write_density(self, psi, path):
+        """Write |psi|^2 as a binary file of Nx*Ny*Nz float64 values, row-major
+        [x][y][z] (read back with numpy.fromfile(path).reshape(n))."""
+        self._check_state(psi)
+        check(self.lib.dgpe_write_density(self.handle, _ptr(psi), str(path).encode()))
+
     def observables(self, psi, amp=1.0):
         """Norm, chemical potential, energy and parts, rms sizes (synchronises)."""
         self._check_state(psi)
         o = _lib.DgpeObs()
         check(self.lib.dgpe_energy_mu_rms(self.handle, _ptr(psi), float(amp), ctypes.byref(o)))
-        return {"norm": o.norm, "mu": o.mu, "energy": o.energy, "e_kin": o.e_kin,
-                "e_trap": o.e_trap, "e_contact": o.e_contact, "e_dd": o.e_dd,
-                "rms": tuple(o.rms[i] for i in range(4))}
+        return _obs_dict(o)
 
     def adjoint(self, psi0, amp, ckpt_every=20, objective="energy", target=None,
                 want_psi_final=True, want_dpsi0=True):
@@ -223,6 +252,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _obs_dict(o):
+    return {"norm": o.norm, "mu": o.mu, "energy": o.energy, "e_kin": o.e_kin,
+            "e_trap": o.e_trap, "e_contact": o.e_contact, "e_dd": o.e_dd,
+            "rms": tuple(o.rms[i] for i in range(4))}
 
 
 def knot_matrix(nknots, nsteps, dt):

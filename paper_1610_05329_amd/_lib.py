@@ -25,7 +25,8 @@ STATUS_NAMES = {
 }
 DGPE_IMAG, DGPE_REAL, DGPE_F64, DGPE_F32 = 0, 1, 0, 2
 PARAM = {"g": 0, "gd": 1, "nu": 2, "lambda": 3, "gamma": 4, "dt": 5, "real_time": 6, "fast_fft": 7,
-         "fused_y": 8}
+         "fused_y": 8, "scheme": 9}
+SCHEME = {"lie": 0, "strang": 1}
 OBJECTIVE = {"energy": 0, "overlap": 1}
 NPASS = 8
 NOALLOC_MAX_BYTES = 64 << 20  # DGPE_NOALLOC_MAX_BYTES
@@ -52,7 +53,11 @@ SIGNATURES = {
     "dgpe_plan_set_stream": (c_int32, [c_void_p, c_void_p]),
     "dgpe_plan_fused_y": (c_int32, [c_void_p]),
     "dgpe_step": (c_int32, [c_void_p, c_void_p, c_int32, P_double]),
+    "dgpe_ground_state": (c_int32, [c_void_p, c_void_p, c_double, c_int32, c_int32, P_int32,
+                                    P_double, ctypes.POINTER(DgpeObs)]),
     "dgpe_potential": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "dgpe_density": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "dgpe_write_density": (c_int32, [c_void_p, c_void_p, c_char_p]),
     "dgpe_energy_mu_rms": (c_int32, [c_void_p, c_void_p, c_double, ctypes.POINTER(DgpeObs)]),
     "dgpe_adjoint_workspace_bytes": (c_size_t, [c_void_p, c_int32, c_int32]),
     "dgpe_step_adjoint": (c_int32, [c_void_p, c_void_p, c_int32, P_double, c_int32, c_int32,

@@ -333,8 +333,8 @@ struct PassTimer {
 template <typename T>
 bool use_fused_y(const Plan& p) {
     const size_t state = (size_t)p.n[0] * p.n[1] * p.n[2] * 2 * sizeof(T);
-    return p.fuse_y && p.fast && p.imag && p.n[1] / 16 <= 16 && state < (size_t(1) << 32) &&
-           fast_c2r_step_yfused_ok<T>(p);
+    return p.fuse_y && p.fast && p.imag && p.scheme == 0 && p.n[1] / 16 <= 16 &&
+           state < (size_t(1) << 32) && fast_c2r_step_yfused_ok<T>(p);
 }
 
 bool fused_y(const Plan& p) { return p.f32 ? use_fused_y<float>(p) : use_fused_y<double>(p); }
@@ -346,6 +346,54 @@ bool use_folded_norm(const Plan& p) {
     return use_fused_y<T>(p) && fast_rows_sigma_ok<T>(p);
 }
 
+// The nonlinear phase of the fused z pass runs over dt_nl instead of dt while
+// this guard lives.
+struct NonlinearStep {
+    Plan& p;
+    NonlinearStep(Plan& plan, double dt_nl) : p(plan) { p.dt_nl = dt_nl; }
+    ~NonlinearStep() { p.dt_nl = p.dt; }
+};
+
+// nsteps symmetric (Strang) steps in place: nonlinear over dt/2 from the
+// density of the incoming state, the three sweeps over dt, nonlinear over dt/2
+// from the density after the sweeps, then (imaginary time) renormalisation.
+// The leading half runs inside the fused z pass.  In real time the phase
+// keeps |psi|, so the trailing half of one step and the leading half of the
+// next see the same density and run as one phase over dt (trap amplitude the
+// mean of the two steps'); the last step's trailing half is a pass of its own.
+// In imaginary time each trailing half convolves the density after the sweeps
+// and reduces the norm of its result (applied lazily by the next step).
+template <typename T>
+dgpe_status run_steps_strang(Plan& p, void* psi, int nsteps, const double* amp, PassTimer& t) {
+    double* sigma = p.scal;
+    for (int s = 0; s < nsteps; ++s) {
+        const double a = amp ? amp[s] : 1.0;
+        const double* sg = (p.imag && s > 0) ? sigma : nullptr;
+        const bool merged = !p.imag && s > 0;
+        const double a_nl = merged ? 0.5 * ((amp ? amp[s - 1] : 1.0) + a) : a;
+        DGPE_PASS(t, 0, (launch_r2c_density<T>(p, psi, sg)));
+        DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
+        DGPE_PASS(t, 2, (launch_xmul<T>(p)));
+        DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
+        {
+            NonlinearStep half(p, merged ? p.dt : 0.5 * p.dt);
+            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, psi, psi, sg, a_nl)));
+        }
+        DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
+        DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, nullptr)));
+        if (p.imag || s + 1 == nsteps) {  // the trailing half as a pass of its own
+            dgpe_status st = convolve_density<T>(p, psi, nullptr);
+            if (st != DGPE_OK) return st;
+            DGPE_HIP(launch_c2r_phi<T>(p, p.phi));
+            int nb = 0;
+            DGPE_HIP(launch_nonlinear<T>(p, psi, p.phi, 0.5 * p.dt, a, p.red, &nb));
+            if (p.imag) DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb, sigma)));
+        }
+    }
+    if (p.imag && nsteps > 0) DGPE_HIP(launch_scale<T>(p, psi, sigma));
+    return DGPE_OK;
+}
+
 // nsteps steps in place on psi; with psi_in, the first step reads psi_in
 // instead (out of place) and, with phi_out, also writes Phi of psi_in's density.
 template <typename T>
@@ -353,6 +401,7 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
                       const void* psi_in = nullptr, void* phi_out = nullptr) {
     PassTimer none;
     PassTimer& t = tm ? *tm : none;
+    if (p.scheme == 1 && !psi_in && !phi_out) return run_steps_strang<T>(p, psi, nsteps, amp, t);
     double* sigma = p.scal;
     void* car = use_fused_y<T>(p) ? p.phi : nullptr;
     const size_t car_bytes = (size_t)p.n[0] * (p.n[1] / 16) * p.n[2] * 2 * sizeof(T);  // one array
@@ -647,6 +696,8 @@ dgpe_status create_plan(dgpe_plan* out, const int32_t n[3], const double d[3], d
         p->trap[a] = trap[a];
     }
     p->dt = dt;
+    p->dt_nl = dt;
+    p->scheme = 0;
     p->g = g;
     p->gd = gd;
     p->R = cutoff_R > 0 ? cutoff_R : 0.5 * std::min({n[0] * d[0], n[1] * d[1], n[2] * d[2]});
@@ -797,9 +848,14 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "FUSED_Y takes 0 or 1");
             p.fuse_y = value == 1.0;
             return DGPE_OK;
+        case DGPE_PARAM_SCHEME:
+            if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "SCHEME takes 0 or 1");
+            p.scheme = (int)value;
+            return DGPE_OK;
         case DGPE_PARAM_DT:
             if (!(value > 0)) return fail(DGPE_EINVAL, "dt must be > 0");
             p.dt = value;
+            p.dt_nl = value;
             break;
         case DGPE_PARAM_REAL_TIME: {
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "REAL_TIME takes 0 or 1");
@@ -838,6 +894,97 @@ dgpe_status dgpe_step(dgpe_plan plan, void* psi, int32_t nsteps, const double* a
             if (!std::isfinite(amp[i])) return fail(DGPE_EINVAL, "amp must be finite");
     return plan->f32 ? run_steps<float>(*plan, psi, nsteps, amp)
                      : run_steps<double>(*plan, psi, nsteps, amp);
+}
+
+dgpe_status dgpe_ground_state(dgpe_plan plan, void* psi, double tol, int32_t max_steps,
+                              int32_t check_every, int32_t* steps_done, double* dmu_per_step,
+                              dgpe_obs* obs) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    if (!steps_done || !dmu_per_step || !obs)
+        return fail(DGPE_EINVAL, "steps_done, dmu_per_step and obs must be non-NULL");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(DGPE_EINVAL, "tol must be finite and > 0");
+    if (max_steps < 0 || check_every < 1)
+        return fail(DGPE_EINVAL, "max_steps must be >= 0 and check_every >= 1");
+    Plan& p = *plan;
+    if (!p.imag) return fail(DGPE_ESTATE, "the ground state needs an imaginary-time plan");
+    auto obs_of = [&](dgpe_obs* o) {
+        return p.f32 ? observables_impl<float>(p, psi, 1.0, o) : observables_impl<double>(p, psi, 1.0, o);
+    };
+    dgpe_obs o{};
+    if ((st = obs_of(&o)) != DGPE_OK) return st;
+    double mu = o.mu, rate = INFINITY;
+    int done = 0;
+    while (done < max_steps) {
+        const int k = std::min(check_every, max_steps - done);
+        st = p.f32 ? run_steps<float>(p, psi, k, nullptr) : run_steps<double>(p, psi, k, nullptr);
+        if (st != DGPE_OK) return st;
+        done += k;
+        if ((st = obs_of(&o)) != DGPE_OK) return st;
+        rate = std::fabs(o.mu - mu) / k;
+        mu = o.mu;
+        if (rate < tol) break;
+    }
+    *steps_done = done;
+    *dmu_per_step = rate;
+    *obs = o;
+    return DGPE_OK;
+}
+
+dgpe_status dgpe_density(dgpe_plan plan, const void* psi, void* out) {
+    if (!plan) return fail(DGPE_EINVAL, "plan is NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    if ((st = check_ptr(out, "out")) != DGPE_OK) return st;
+    DGPE_HIP(plan->f32 ? launch_density<float>(*plan, psi, out) : launch_density<double>(*plan, psi, out));
+    return DGPE_OK;
+}
+
+dgpe_status dgpe_write_density(dgpe_plan plan, const void* psi, const char* path) {
+    if (!plan || !path) return fail(DGPE_EINVAL, "plan and path must be non-NULL");
+    if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
+    dgpe_status st = check_ptr(psi, "psi");
+    if (st != DGPE_OK) return st;
+    Plan& p = *plan;
+    const size_t rsz = p.f32 ? 4 : 8;
+    // the density of the whole grid in the Phi buffer, then x-planes to the
+    // host through a bounded buffer, widened to FP64 and appended in order
+    DGPE_HIP(p.f32 ? launch_density<float>(p, psi, p.phi) : launch_density<double>(p, psi, p.phi));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(DGPE_EINVAL, std::string("cannot open ") + path + " for writing");
+    const size_t plane = (size_t)p.n[1] * p.n[2];
+    const size_t chunk_planes = std::max<size_t>(1, ((size_t)8 << 20) / (plane * rsz));
+    std::vector<unsigned char> raw(chunk_planes * plane * rsz);
+    std::vector<double> wide(chunk_planes * plane);
+    for (size_t x0 = 0; x0 < (size_t)p.n[0]; x0 += chunk_planes) {
+        const size_t np = std::min(chunk_planes, (size_t)p.n[0] - x0);
+        const size_t cnt = np * plane;
+        hipError_t e = hipMemcpyAsync(raw.data(), (const char*)p.phi + x0 * plane * rsz, cnt * rsz,
+                                      hipMemcpyDeviceToHost, p.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p.stream);
+        if (e != hipSuccess) {
+            std::fclose(f);
+            return fail(DGPE_EHIP, std::string("density download: ") + hipGetErrorString(e));
+        }
+        for (size_t i = 0; i < cnt; ++i) {
+            if (p.f32) {
+                float v;
+                std::memcpy(&v, raw.data() + i * 4, 4);
+                wide[i] = v;
+            } else {
+                std::memcpy(&wide[i], raw.data() + i * 8, 8);
+            }
+        }
+        if (std::fwrite(wide.data(), sizeof(double), cnt, f) != cnt) {
+            std::fclose(f);
+            return fail(DGPE_EINVAL, std::string("short write to ") + path);
+        }
+    }
+    if (std::fclose(f) != 0) return fail(DGPE_EINVAL, std::string("cannot close ") + path);
+    return DGPE_OK;
 }
 
 dgpe_status dgpe_potential(dgpe_plan plan, const void* psi, void* phi) {
@@ -880,6 +1027,7 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
     if (plan_live(*plan) != DGPE_OK) return DGPE_ESTATE;
     Plan& p = *plan;
     if (p.imag) return fail(DGPE_ESTATE, "the adjoint needs a real-time plan");
+    if (p.scheme != 0) return fail(DGPE_ESTATE, "the adjoint is that of the first-order step");
     if (nsteps < 1 || ckpt_every < 1) return fail(DGPE_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (!amp || !J || !dJ_damp || !dJ_dtrap) return fail(DGPE_EINVAL, "amp, J, dJ_damp, dJ_dtrap required");
     for (int i = 0; i <= nsteps; ++i)

@@ -45,6 +45,9 @@ struct Plan {
     int n[3];
     double d[3];
     double dt;
+    double dt_nl;  // time step of the nonlinear phase in the fused z pass (dt, or dt/2
+                   // in the first step of the symmetric scheme)
+    int scheme;    // 0: first-order (Lie) step; 1: symmetric (Strang) step
     double trap[3];
     double g, gd, R;
     bool imag, f32;
@@ -130,6 +133,14 @@ template <typename T>
 hipError_t launch_overlap_seed(const Plan& p, void* lam, const void* target, const double* coef);
 template <typename T>
 hipError_t launch_copy(const Plan& p, void* dst, const void* src);
+// |psi|^2 into out (real, plan precision)
+template <typename T>
+hipError_t launch_density(const Plan& p, const void* psi, void* out);
+// the nonlinear step alone over time dt with potential phi (a real grid array
+// of Phi[|psi|^2]); imaginary time: per-block sums of |psi'|^2 into partials
+template <typename T>
+hipError_t launch_nonlinear(const Plan& p, void* psi, const void* phi, double dt, double amp,
+                            double* partials, int* nblocks);
 
 // Deterministic fixed-order reduction of partials[nblocks][width] into
 // out[width] (FP64, Neumaier-compensated); optional 1/(sum[0] dV) into sigma.

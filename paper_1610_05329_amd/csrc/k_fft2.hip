@@ -1015,7 +1015,7 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
     const cx<double> kappa = {k.re, k.im};
     const cx_coef ky = cn_kappa(p, 1, false);
     const cx<double> kappay = {ky.re, ky.im};
-    Phys2 ph{p.dt, p.g, p.gd, amp, p.imag ? 1 : 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
+    Phys2 ph{p.dt_nl, p.g, p.gd, amp, p.imag ? 1 : 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
              p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
              0.5 * p.trap[2] * p.trap[2]};
     const cx<double>* tab = (const cx<double>*)p.cntab[2][0];

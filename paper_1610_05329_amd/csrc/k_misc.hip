@@ -210,6 +210,53 @@ __global__ void __launch_bounds__(kRedThreads)
     }
 }
 
+// The nonlinear step on its own (the half steps of the symmetric scheme):
+// theta = dt (a V0 + g |psi|^2 + gd Phi) from the state's own density;
+// psi <- psi exp(-theta) with per-block FP64 sums of |psi'|^2 (imaginary time)
+// or psi <- psi exp(-i theta) (real time).  Phi is the potential of |psi|^2.
+template <typename T, bool IMAG>
+__global__ void __launch_bounds__(kRedThreads)
+    k_nonlinear(cx<T>* __restrict__ psi, const T* __restrict__ phi, Geo g, double dt, double gg,
+                double gdd, double amp, double* __restrict__ partials) {
+    __shared__ double red[kRedThreads / 64];
+    double acc = 0.0;
+    const size_t nt = (size_t)g.nx * g.ny * g.nz;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nt;
+         i += (size_t)gridDim.x * blockDim.x) {
+        int ix, iy, iz;
+        coords(g, i, ix, iy, iz);
+        const T x = T(ix - g.hx) * T(g.dx), y = T(iy - g.hy) * T(g.dy), z = T(iz - g.hz) * T(g.dz);
+        const T v0 = T(g.cx) * x * x + T(g.cy) * y * y + T(g.cz) * z * z;
+        const cx<T> u = psi[i];
+        const T th = T(dt) * (T(amp) * v0 + T(gg) * abs2(u) + T(gdd) * phi[i]);
+        cx<T> w;
+        if (IMAG) {
+            const T e = exp(-th);
+            w = cx<T>{u.x * e, u.y * e};
+            acc += double(w.x) * w.x + double(w.y) * w.y;
+        } else {
+            T sn, cs;
+            sin_cos(th, &sn, &cs);
+            w = cx<T>{u.x * cs + u.y * sn, u.y * cs - u.x * sn};
+        }
+        psi[i] = w;
+    }
+    if (IMAG) {
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// n = |psi|^2 with FP64 products, rounded once to the plan precision
+template <typename T>
+__global__ void k_density(const cx<T>* __restrict__ psi, T* __restrict__ out, size_t nt) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nt;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const cx<T> u = psi[i];
+        out[i] = T(double(u.x) * double(u.x) + double(u.y) * double(u.y));
+    }
+}
+
 // partial sums of conj(target) psi (re, im)
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
@@ -322,6 +369,28 @@ hipError_t launch_overlap_seed(const Plan& p, void* lam, const void* target, con
 }
 
 template <typename T>
+hipError_t launch_nonlinear(const Plan& p, void* psi, const void* phi, double dt, double amp,
+                            double* partials, int* nblocks) {
+    const int nb = observables_blocks(p);
+    if (nblocks) *nblocks = nb;
+    if (p.imag)
+        hipLaunchKernelGGL((k_nonlinear<T, true>), dim3(nb), dim3(kRedThreads), 0, p.stream,
+                           (cx<T>*)psi, (const T*)phi, geo_of(p), dt, p.g, p.gd, amp, partials);
+    else
+        hipLaunchKernelGGL((k_nonlinear<T, false>), dim3(nb), dim3(kRedThreads), 0, p.stream,
+                           (cx<T>*)psi, (const T*)phi, geo_of(p), dt, p.g, p.gd, amp, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_density(const Plan& p, const void* psi, void* out) {
+    const size_t nt = (size_t)p.n[0] * p.n[1] * p.n[2];
+    hipLaunchKernelGGL((k_density<T>), dim3(grid_for(nt, 256, 16384)), dim3(256), 0, p.stream,
+                       (const cx<T>*)psi, (T*)out, nt);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_copy(const Plan& p, void* dst, const void* src) {
     const size_t nt = (size_t)p.n[0] * p.n[1] * p.n[2];
     return hipMemcpyAsync(dst, src, nt * sizeof(cx<T>), hipMemcpyDeviceToDevice, p.stream);
@@ -337,6 +406,9 @@ hipError_t launch_copy(const Plan& p, void* dst, const void* src) {
                                            double*, int*);                                        \
     template hipError_t launch_overlap<T>(const Plan&, const void*, const void*, double*, int*);  \
     template hipError_t launch_overlap_seed<T>(const Plan&, void*, const void*, const double*);   \
+    template hipError_t launch_nonlinear<T>(const Plan&, void*, const void*, double, double,       \
+                                            double*, int*);                                       \
+    template hipError_t launch_density<T>(const Plan&, const void*, void*);                       \
     template hipError_t launch_copy<T>(const Plan&, void*, const void*);
 DGPE_INST(float)
 DGPE_INST(double)

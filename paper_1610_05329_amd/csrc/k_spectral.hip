@@ -605,7 +605,7 @@ hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, con
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
     const cx<double> kappa = {k.re, k.im};
-    Phys ph{p.dt, p.g, p.gd, amp, p.imag ? 1 : 0};
+    Phys ph{p.dt_nl, p.g, p.gd, amp, p.imag ? 1 : 0};
     const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
     const int S = p.lc.seg[2];
     const bool guard = (p.n[2] % S) != 0;
