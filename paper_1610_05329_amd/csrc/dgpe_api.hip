@@ -120,11 +120,15 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
         const int S = 16;
         const int nseg = (L + S - 1) / S;
         // FP32 imaginary time keeps FP32 recurrences (1024-thread blocks); FP64
-        // and real-time recurrences are FP64 (512-thread blocks)
+        // and real-time recurrences are FP64
         const bool narrow = f32 && imag;
-        // FP64 recurrences hold ~150 VGPRs (3 waves per SIMD): blocks of at
-        // most 256 threads keep 3 blocks per CU resident
-        const int tmax = narrow ? 1024 : 256;
+        // FP64 states hold ~140 VGPRs (3 waves per SIMD): blocks of at most 256
+        // threads keep 3 blocks per CU resident.  FP32 states in real time hold
+        // the line in FP32 between the FP64 recurrences (~114 VGPRs): blocks of
+        // up to 512 threads, so that 512-point lines (32 segments) still get 16
+        // columns, 128-byte runs (8 columns: 264 us, 16: 230 us, 32 in
+        // 1024-thread blocks: 315 us at 512 x 512 x 256)
+        const int tmax = narrow ? 1024 : f32 ? 512 : 256;
         const size_t asz = narrow ? 8 : 16;
         // measured at 256^3: 32 columns per block (FP32 recurrences) and 16
         // (FP64 recurrences) overlap loads and solves better than 64

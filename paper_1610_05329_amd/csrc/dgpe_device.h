@@ -651,27 +651,50 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
         dl[seg * nlines + line] = dcur;
     }
     __syncthreads();
+    // Values stored narrower than the arithmetic (FP32 state, FP64 real-time
+    // recurrences) take the back substitution twice: once without stores for
+    // the segment's first value, then from the true right carry, storing each
+    // x once.  Storing the zero-carry x and adding Q_i x_right afterwards
+    // rounds those values twice, and that double rounding drifts the norm
+    // (about 6e-6 over 1000 real-time steps at 128^3); rounding the forward d
+    // does not.
+    constexpr bool kTwice = sizeof(VS) < sizeof(A);
+    cx<A> c = {A(0), A(0)};
     if (act) {
         // 2. true d before the segment's first point, from the segments on the
         // left (P correction), then back substitution from a zero carry
-        const cx<A> c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
+        c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
         cx<A> xcur = {A(0), A(0)};
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
             if (!GUARD || i < cnt) {
                 const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
                 xcur = d + kmul<RC>(alpha(i), xcur);
-                v[i] = to_store<VS>(xcur);
+                if constexpr (!kTwice) v[i] = to_store<VS>(xcur);
             }
         }
         xf[seg * nlines + line] = xcur;
     }
     __syncthreads();
     if (act) {
-        cx<A> c = carry_chain<A, RC, true>(xf, qbeg, seg + 1, nseg, nlines, line);
+        const cx<A> cr = carry_chain<A, RC, true>(xf, qbeg, seg + 1, nseg, nlines, line);
+        if constexpr (kTwice) {
+            // 3. back substitution from the true x after the segment
+            cx<A> xcur = cr;
 #pragma unroll
-        for (int i = 0; i < S; ++i)
-            if (!GUARD || i < cnt) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[tb + i]), c));
+            for (int i = S - 1; i >= 0; --i) {
+                if (!GUARD || i < cnt) {
+                    const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
+                    xcur = d + kmul<RC>(alpha(i), xcur);
+                    v[i] = to_store<VS>(xcur);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (!GUARD || i < cnt)
+                    v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[tb + i]), cr));
+        }
     }
 }
 
@@ -730,12 +753,16 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
     // P correction and back substitution from a zero carry.  FP64 factors are
     // read again here rather than kept live since the forward pass (64 registers)
     if constexpr (sizeof(A) == 8) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // (narrower storage than arithmetic: the back substitution runs twice, the
+    // second time from the true right carry, so that each x is rounded once;
+    // see cn_segment_solve)
+    constexpr bool kTwice = sizeof(VS) < sizeof(A);
     cx<A> xcur = zero;
 #pragma unroll
     for (int i = S - 1; i >= 0; --i) {
         const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c);
         xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
-        v[i] = to_store<VS>(xcur);
+        if constexpr (!kTwice) v[i] = to_store<VS>(xcur);
     }
     // scan from the right: true x at the start of each segment
     a = widen<A>(qbeg[seg]);
@@ -748,10 +775,22 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
             a = kmul<RC>(a, ap);
         }
     }
-    c = shfl_down_c(b, 1, NSEG);
-    if (seg == NSEG - 1) c = zero;
+    cx<A> cr = shfl_down_c(b, 1, NSEG);
+    if (seg == NSEG - 1) cr = zero;
+    if constexpr (kTwice) {
+        // the factors are read again (not kept live through the scan)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        xcur = cr;
 #pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[i]), c));
+        for (int i = S - 1; i >= 0; --i) {
+            const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c);
+            xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
+            v[i] = to_store<VS>(xcur);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < S; ++i) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[i]), cr));
+    }
 }
 
 }  // namespace dgpe

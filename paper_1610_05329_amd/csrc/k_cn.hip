@@ -52,7 +52,7 @@ __device__ __forceinline__ cx<double> tab_at(const cx<double>* t, int i) {
 // ([Ny/16][Nz/ZB][Nx][ZB][2]: the blocks of one segment and z range read one
 // contiguous tile), and E, Q from the y tables.
 template <typename T, int S, bool RC, bool GUARD, bool YC>
-__global__ void __launch_bounds__(YC || sizeof(cn_acc_t<T, RC>) == 8 ? kMaxThreads / 2 : kMaxThreads)
+__global__ void __launch_bounds__(YC || sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads)
 __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8)))
     k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab tg,
                  cx<double> kappa64, double* __restrict__ norm_partials,
@@ -76,7 +76,11 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     // clamped: the writes below are unconditional so the loads stay ahead of
     // the state loads; see tab_stage), then the state, then staging.
     const int i0 = min(tid, L - 1), s0 = min(tid, nseg - 1);
-    const cx<double> a0 = tab_at<RC>(tg.a, i0), p0 = tab_at<RC>(tg.p, i0), q0 = tab_at<RC>(tg.q, i0);
+    // the Q table serves only solves that store at the arithmetic's precision
+    // (a narrower store runs the back substitution twice instead)
+    constexpr bool kQ = sizeof(T) >= sizeof(A);
+    const cx<double> a0 = tab_at<RC>(tg.a, i0), p0 = tab_at<RC>(tg.p, i0);
+    const cx<double> q0 = kQ ? tab_at<RC>(tg.q, i0) : cx<double>{0.0, 0.0};
     const cx<double> pe0 = tab_at<RC>(tg.pend, s0), qb0 = tab_at<RC>(tg.qbeg, s0);
     const cx<A> kappa = narrow_tab<A>(kappa64);
     const int ncb = C >> logZB;
@@ -104,14 +108,17 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     const uint32_t cstep = (uint32_t)C * csz;  // one x step of the state
     const uint32_t foff = ((uint32_t)e0 * (uint32_t)C + (uint32_t)(c0 + cl)) * csz;
     const __amdgpu_buffer_rsrc_t rf = buf_rsrc(f, YC ? (uint32_t)L * cstep : 0u);
-    cx<A> v[S];
+    // the line's values are held in the state's precision between the
+    // recurrences, which run in A (FP64 in real time): only the factors must
+    // not be rounded to FP32, the stored intermediates may
+    cx<T> v[S];
 #pragma unroll
     for (int i = 0; i < S; ++i)
         if (!GUARD || i < cnt) {
             if constexpr (YC)
-                v[i] = widen<A>(buf_load_cx<T>(rf, foff, i * cstep));
+                v[i] = buf_load_cx<T>(rf, foff, i * cstep);
             else
-                v[i] = widen<A>(base[(size_t)(e0 + i) * C]);
+                v[i] = base[(size_t)(e0 + i) * C];
         }
     if constexpr (YC) {
         const uint32_t kst = (uint32_t)ZB * 2 * csz;  // one x step of the pairs
@@ -139,32 +146,33 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
 #pragma unroll
         for (int i = 0; i < S; ++i)
             if (!GUARD || i < cnt)
-                v[i] = v[i] + kmul<RC>(ey, widen<A>(cc[i][0])) + kmul<RC>(qy, widen<A>(cc[i][1]));
+                v[i] = to_store<T>(widen<A>(v[i]) + kmul<RC>(ey, widen<A>(cc[i][0])) +
+                                   kmul<RC>(qy, widen<A>(cc[i][1])));
     }
     ta[i0 + i0 / S] = narrow_tab<A>(a0);
     tp[i0 + i0 / S] = narrow_tab<A>(p0);
-    tq[i0 + i0 / S] = narrow_tab<A>(q0);
+    if constexpr (kQ) tq[i0 + i0 / S] = narrow_tab<A>(q0);
     pe[s0] = narrow_tab<A>(pe0);
     qb[s0] = narrow_tab<A>(qb0);
     for (int i = tid + nthr; i < L; i += nthr) {  // lines longer than the block
         const int ip = i + i / S;
         ta[ip] = narrow_tab<A>(tg.a[i]);
         tp[ip] = narrow_tab<A>(tg.p[i]);
-        tq[ip] = narrow_tab<A>(tg.q[i]);
+        if constexpr (kQ) tq[ip] = narrow_tab<A>(tg.q[i]);
     }
     for (int i = tid + nthr; i < nseg; i += nthr) {
         pe[i] = narrow_tab<A>(tg.pend[i]);
         qb[i] = narrow_tab<A>(tg.qbeg[i]);
     }
-    cx<A> lastv = v[S - 1];
+    cx<T> lastv = v[S - 1];
     if (GUARD) {
 #pragma unroll
         for (int i = 0; i < S; ++i)
             if (i == cnt - 1) lastv = v[i];
     }
     if (cnt > 0) {
-        A1[seg * ZB + cl] = v[0];
-        A2[seg * ZB + cl] = lastv;
+        A1[seg * ZB + cl] = widen<A>(v[0]);
+        A2[seg * ZB + cl] = widen<A>(lastv);
     }
     __syncthreads();
     cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
@@ -403,12 +411,12 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
     const int seg = tid >> logB;
     const int e0 = seg * SZ;
     const int cnt = (seg < nseg) ? min(SZ, Nz - e0) : 0;
-    cx<A> v[SZ];
+    cx<T> v[SZ];
     cx<A> left = {A(0), A(0)}, right = {A(0), A(0)};
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
-            if (!GUARD || i < cnt) v[i] = widen<A>(P[(e0 + i) * ES + bl]);
+            if (!GUARD || i < cnt) v[i] = P[(e0 + i) * ES + bl];
         if (e0 > 0) left = widen<A>(P[(e0 - 1) * ES + bl]);
         if (e0 + cnt < Nz) right = widen<A>(P[(e0 + cnt) * ES + bl]);
     }

@@ -20,6 +20,20 @@ constexpr int rows_per_block() {
     return nb;
 }
 
+// Columns per block of the x pass: as rows_per_block for lines shorter than
+// 384 points; longer lines take up to 64 KB of LDS and 512 threads, so that
+// each row of the block's tile is a run of at least 128 bytes (8 columns,
+// 64-byte runs, held the 512-point pass to half the HBM bandwidth; 32
+// columns, 128 KB, one block per CU, were slower still: 185 against 135 us
+// at 512 x 512 x 256).
+template <typename T, int R1, int L>
+constexpr int xmul_cols() {
+    if (L < 384) return rows_per_block<T, R1, L>();
+    int nb = 32;
+    while (nb > 1 && (nb * L * 2 * (int)sizeof(T) > 64 * 1024 || nb * R1 > 512)) nb >>= 1;
+    return nb;
+}
+
 // ---------------------------------------------------------------------------
 // P2 / P4: FFT along contiguous rows of length L = R1 R2 (the y axis of S).
 // Lanes: t fastest (t < R1 threads per row), NB rows per block.
@@ -79,11 +93,11 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 // Lanes: b fastest (NB columns), t < R1 threads per column.
 // ---------------------------------------------------------------------------
 template <typename T, int R1, int R2>
-__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+__global__ void __launch_bounds__((xmul_cols<T, R1, R1 * R2>() * R1))
     k_xmul2(cx<T>* __restrict__ spec, int Ny, const cx<T>* __restrict__ tw,
             const T* __restrict__ ukern) {
     constexpr int L = R1 * R2;  // Nx
-    constexpr int NB = rows_per_block<T, R1, L>();
+    constexpr int NB = xmul_cols<T, R1, L>();
     constexpr int NT = NB * R1;
     __shared__ cx<T> xb[NB * L];
     __shared__ cx<T> stw[L];
@@ -138,6 +152,94 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < R2; ++u) v[u] = xb[(t * R2 + u) * NB + b];
+    rdft<T, R2, true>(v);
+#pragma unroll
+    for (int l = 0; l < R2; ++l) base[(size_t)(t + R1 * l) * Ny] = v[l];
+}
+
+// P3 for long lines with R1 = 2 R2 (the 512-point split 32 x 16): as k_xmul2,
+// but the size-R1 DFTs of phase B are split over the lane pair (t, t ^ 1):
+// lane h = t & 1 of group g = t >> 1 (the phase-B index k2) transforms the
+// R1/2 values with n1 = h + 2m, and one radix-2 step across the pair (wave
+// shuffles: the pair is NB lanes apart in one wave) joins them,
+//   X[k] = E[k] + W_R1^k O[k],  X[k + R1/2] = E[k] - W_R1^k O[k]
+// (E from the even n1, O from the odd ones).  The inverse undoes it in the
+// opposite order: E'[k] = X[k] + X[k + R1/2], O'[k] = (X[k] - X[k + R1/2])
+// W_R1^-k, then inverse DFTs of size R1/2.  Every thread then works in both
+// phases with R1/2 = R2 values, which keeps 16-column tiles (128-byte runs)
+// at four waves per SIMD.
+template <typename T, int R1, int R2>
+__global__ void __launch_bounds__((xmul_cols<T, R1, R1 * R2>() * R1))
+    k_xmul2s(cx<T>* __restrict__ spec, int Ny, const cx<T>* __restrict__ tw,
+             const T* __restrict__ ukern) {
+    static_assert(R1 == 2 * R2, "the pair split needs R1 = 2 R2");
+    constexpr int L = R1 * R2;  // Nx
+    constexpr int NB = xmul_cols<T, R1, L>();
+    static_assert(NB <= 32, "lane pairs must share a wave");
+    constexpr int NT = NB * R1;
+    constexpr int H = R1 / 2;
+    __shared__ cx<T> xb[NB * L];
+    __shared__ cx<T> stw[L];
+    const int tid = threadIdx.x;
+    const int b = tid % NB, t = tid / NB;
+    const int g = t >> 1, h = t & 1;
+    const int ngy = Ny / NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int kz = bid / ngy;
+    const int y0 = (bid - kz * ngy) * NB;
+    TabRegs<cx<T>, L, NT> rtw;
+    tab_issue(rtw, tw, tid);
+    cx<T>* base = spec + (size_t)kz * L * Ny + y0 + b;
+    cx<T> v[R2];
+#pragma unroll
+    for (int n = 0; n < R2; ++n) v[n] = base[(size_t)(t + R1 * n) * Ny];
+    // this lane's outputs of phase B are X[kx = g + R2 (k + H h)], k < H
+    const int hy = Ny / 2 + 1;
+    const T* ucol = ukern + (size_t)kz * (L / 2 + 1) * hy + min(y0 + b, Ny - y0 - b);
+    T uk[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const int kx = g + R2 * (k + H * h);
+        uk[k] = ucol[(size_t)min(kx, L - kx) * hy];
+    }
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
+    __syncthreads();
+    // phase A: DFT over n2 of x[t + R1 n2], twiddle W_L^{t k2}
+    rdft<T, R2, false>(v);
+    twiddle_phase<T, R2, false>(v, t, stw);
+#pragma unroll
+    for (int k = 0; k < R2; ++k) xb[(k * R1 + t) * NB + b] = v[k];
+    __syncthreads();
+    // phase B, half h of group g: DFT of size H over n1 = h + 2m
+    cx<T> w[H];
+#pragma unroll
+    for (int m = 0; m < H; ++m) w[m] = xb[(g * R1 + h + 2 * m) * NB + b];
+    rdft<T, H, false>(w);
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const cx<T> q = {__shfl_xor(w[k].x, NB), __shfl_xor(w[k].y, NB)};
+        const cx<T> e = h ? q : w[k];
+        const cx<T> o = cmul(h ? w[k] : q, ctw<T, R1, false>(k));
+        const cx<T> x = h ? e - o : e + o;
+        // multiply by U_R / Nt
+        w[k] = uk[k] * x;
+    }
+    // inverse of the pair step, then inverse DFTs of size H
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+        const cx<T> q = {__shfl_xor(w[k].x, NB), __shfl_xor(w[k].y, NB)};
+        w[k] = h ? cmul(q - w[k], ctw<T, R1, true>(k)) : w[k] + q;
+    }
+    rdft<T, H, true>(w);
+    __syncthreads();  // every lane has read its phase-A values
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+        const int n1 = h + 2 * m;
+        xb[(g * R1 + n1) * NB + b] = cmulc(w[m], stw[n1 * g]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k2] = xb[(k2 * R1 + t) * NB + b];
     rdft<T, R2, true>(v);
 #pragma unroll
     for (int l = 0; l < R2; ++l) base[(size_t)(t + R1 * l) * Ny] = v[l];
@@ -866,13 +968,29 @@ bool fast_rows(const Plan& p, bool inverse, const double* npart, int nnpart, dou
 }
 
 template <typename T>
+int fast_xmul_cols(int L) {
+    switch (L) {
+#define DGPE_CASE(A, B) \
+    case A * B: return xmul_cols<T, A, A * B>();
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return 0;
+    }
+}
+
+template <typename T>
 bool fast_xmul(const Plan& p) {
     const int L = p.n[0];
     const Split2 s = fast_split(L);
     if (!s.r1) return false;
-    const int nb = fast_rows_per_block<T>(L);
+    const int nb = fast_xmul_cols<T>(L);
     if (p.n[1] % nb) return false;
     const int blocks = (p.n[2] / 2 + 1) * (p.n[1] / nb);
+    if (L == 512) {  // R1 = 2 R2: phase B split over lane pairs
+        hipLaunchKernelGGL((k_xmul2s<T, 32, 16>), dim3(blocks), dim3(nb * 32), 0, p.stream,
+                           (cx<T>*)p.spec, p.n[1], (const cx<T>*)p.tw[0], (const T*)p.ukern);
+        return true;
+    }
     switch (L) {
 #define DGPE_CASE(A, B)                                                                              \
     case A * B:                                                                                      \
