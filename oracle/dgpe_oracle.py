@@ -37,15 +37,21 @@ Variants of the same method (the paper's programs use the form above):
     nonlinear over dt/2 from the new density, then step 3;
   - propagation to the ground state in imaginary time, stopped when the
     chemical potential changes by less than a tolerance per step ("Solution
-    method": imaginary-time propagation to the stationary state).
+    method": imaginary-time propagation to the stationary state);
+  - the quasi-two-dimensional equation of the 2d programs (program title;
+    "Nature of problem": one, two and three spatial dimensions), the tight
+    axis integrated out over its trap's Gaussian ground state (section below).
 
 Parity pins (tests/test_oracle_pins.py): brute-force DFT convolution, radial
 quadrature of the cut-off kernel, the closed-form dipolar energy of an
 anisotropic Gaussian, dense linear solves, exact separable non-interacting
 evolution (Lie and Strang), the harmonic ground-state energy (1 + lam + gam)/2,
 norm conservation, time reversal (and the exact symmetry of the Strang step),
-the second order in dt of the Strang step, the virial theorem and finite
-differences of the adjoint.
+the second order in dt of the Strang step, the virial theorem, finite
+differences of the adjoint, and for the quasi-2D equation: quadrature of the
+3D kernel over the tight axis, the 3D closed-form dipolar energy of axially
+symmetric Gaussians (with the L^-3 image tail), the contact energy of the
+product state and exact separable non-interacting steps.
 """
 from __future__ import annotations
 
@@ -53,12 +59,14 @@ from dataclasses import dataclass, replace
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
+from scipy import special
 
 __all__ = [
     "Params", "grid", "trap_base", "cutoff_factor", "dipolar_kernel",
     "dipolar_potential", "cn_coefficient", "cn_solve_axis", "kinetic_step",
     "nonlinear_step", "step", "strang_step", "evolve", "ground_state", "norm", "observables",
     "hamiltonian_apply", "energy_total", "adjoint_evolve", "overlap_objective",
+    "Params2D", "q2d_kernel", "q2d_potential", "q2d_step", "q2d_evolve", "q2d_observables",
 ]
 
 
@@ -430,3 +438,138 @@ def adjoint_evolve(p: Params, psi0, amp: Sequence[float], objective: str = "ener
         for j in range(3):
             dJ_dtrap[j] += p.dt * an * p.trap[j] * float(np.sum(s * coord2[j]))
     return J, psiN, dJ_da, dJ_dtrap, lam
+
+
+# ----------------------------------------------------------------------------
+# Quasi-two-dimensional programs (the paper's 2d programs)
+# ----------------------------------------------------------------------------
+#
+# A condensate held by a tight harmonic trap of frequency nu_t along one axis
+# stays in that trap's Gaussian ground state phi(t) = exp(-t^2/(2 l^2)) /
+# (pi l^2)^(1/4), l = 1/sqrt(nu_t); integrating the 3D equation over that axis
+# leaves a 2D equation for psi(a, b) on the plane (axes a = first, b = second,
+# [Na][Nb] with b contiguous):
+#   contact  g2 = g int phi^4 dt = g / (sqrt(2 pi) l)
+#   dipolar  U2(q) = int dk_t/(2 pi) U(q, k_t) exp(-k_t^2 l^2 / 2) with the 3D
+#            kernel U(k) = (4 pi/3)(3 cos^2 - 1) of dipoles along a fixed axis
+#            (no spherical cut-off; the plane's own sum has none either):
+#     dipoles along the tight axis ("perp", the XY programs):
+#       U2(q) = (4 pi/3) / (sqrt(2 pi) l) [2 - 3 F(q l / sqrt 2)]
+#     dipoles along the plane's axis b ("inplane", the XZ programs):
+#       U2(q) = (4 pi/3) / (sqrt(2 pi) l) [-1 + 3 (q_b^2/q^2) F(q l / sqrt 2)]
+#     with F(u) = sqrt(pi) u exp(u^2) erfc(u) (F(0) = 0, F -> 1 as u -> inf).
+#   trap V = a/2 (nu_a^2 a^2 + nu_b^2 b^2); the tight axis' constant energy
+#   nu_t/2 is left out of every reported energy.
+# One step is the 3D step with two Crank-Nicolson sweeps (a and b).
+
+@dataclass(frozen=True)
+class Params2D:
+    """Quasi-2D run: plane grid n = (Na, Nb), spacings d, in-plane trap
+    (nu_a, nu_b), tight-axis frequency nu_t, 3D couplings g, gd, and the dipole
+    orientation "perp" (along the tight axis) or "inplane" (along axis b)."""
+
+    n: Tuple[int, int]
+    d: Tuple[float, float]
+    dt: float
+    trap: Tuple[float, float]
+    nu_t: float
+    g: float
+    gd: float
+    imag: bool
+    dipoles: str = "perp"
+
+    @property
+    def ell(self) -> float:
+        return 1.0 / np.sqrt(self.nu_t)
+
+    @property
+    def g2(self) -> float:
+        return self.g / (np.sqrt(2.0 * np.pi) * self.ell)
+
+    @property
+    def dA(self) -> float:
+        return self.d[0] * self.d[1]
+
+
+def q2d_grid(p: Params2D):
+    return tuple((np.arange(p.n[a], dtype=np.float64) - p.n[a] // 2) * p.d[a] for a in range(2))
+
+
+def q2d_trap(p: Params2D):
+    xa, xb = q2d_grid(p)
+    return 0.5 * ((p.trap[0] * xa) ** 2)[:, None] + 0.5 * ((p.trap[1] * xb) ** 2)[None, :]
+
+
+def q2d_kernel(p: Params2D):
+    """U2 on the half spectrum [Na][Nb/2+1] of the real-to-complex DFT along b."""
+    qa = 2.0 * np.pi * np.fft.fftfreq(p.n[0], d=p.d[0])
+    qb = 2.0 * np.pi * np.fft.rfftfreq(p.n[1], d=p.d[1])
+    q2 = qa[:, None] ** 2 + qb[None, :] ** 2
+    u = np.sqrt(q2) * p.ell / np.sqrt(2.0)
+    F = np.sqrt(np.pi) * u * special.erfcx(u)
+    pre = (4.0 * np.pi / 3.0) / (np.sqrt(2.0 * np.pi) * p.ell)
+    if p.dipoles == "perp":
+        return pre * (2.0 - 3.0 * F)
+    if p.dipoles == "inplane":
+        ratio = np.zeros_like(q2)
+        nz = q2 > 0
+        ratio[nz] = np.broadcast_to(qb[None, :] ** 2, q2.shape)[nz] / q2[nz]
+        return pre * (-1.0 + 3.0 * ratio * F)
+    raise ValueError(p.dipoles)
+
+
+def q2d_potential(p: Params2D, field):
+    spec = np.fft.rfftn(field, axes=(0, 1))
+    return np.fft.irfftn(q2d_kernel(p) * spec, s=p.n, axes=(0, 1))
+
+
+def q2d_step(p: Params2D, psi, a: float = 1.0):
+    """Nonlinear step (pre-step density), Crank-Nicolson along a and b, then
+    (imaginary time) renormalisation to sum |psi|^2 dA = 1."""
+    dens = np.abs(psi) ** 2
+    th = a * q2d_trap(p) + p.g2 * dens
+    if p.gd != 0.0:
+        th = th + p.gd * q2d_potential(p, dens)
+    th = p.dt * th
+    psi = psi * (np.exp(-th) if p.imag else np.exp(-1j * th))
+    for axis in (0, 1):
+        c = p.dt / (4.0 * p.d[axis] ** 2)
+        psi = cn_solve_axis(psi, complex(c) if p.imag else 1j * c, axis)
+    if p.imag:
+        psi = psi / np.sqrt(np.sum(np.abs(psi) ** 2) * p.dA)
+    return psi
+
+
+def q2d_evolve(p: Params2D, psi, nsteps: int):
+    psi = np.array(psi, dtype=np.complex128, copy=True)
+    for _ in range(nsteps):
+        psi = q2d_step(p, psi)
+    return psi
+
+
+def q2d_observables(p: Params2D, psi, a: float = 1.0):
+    """As observables() on the plane: E_kin over the two axes (ghost zeros),
+    E_trap, E_c = g2/2 sum n^2, E_dd = gd/2 sum Phi n, all times dA; rms sizes
+    along a and b and in the plane."""
+    dA = p.dA
+    dens = np.abs(psi) ** 2
+    nrm = float(np.sum(dens) * dA)
+    ekin = 0.0
+    for axis in range(2):
+        pad = [(0, 0)] * 2
+        pad[axis] = (1, 1)
+        df = np.diff(np.pad(psi, pad), axis=axis)
+        ekin += 0.5 * float(np.sum(np.abs(df) ** 2)) / p.d[axis] ** 2 * dA
+    etrap = float(np.sum(a * q2d_trap(p) * dens) * dA)
+    ec = 0.5 * p.g2 * float(np.sum(dens * dens) * dA)
+    edd = 0.5 * p.gd * float(np.sum(q2d_potential(p, dens) * dens) * dA) if p.gd != 0.0 else 0.0
+    xa, xb = q2d_grid(p)
+    ma = float(np.sum(dens * (xa ** 2)[:, None]) * dA) / nrm
+    mb = float(np.sum(dens * (xb ** 2)[None, :]) * dA) / nrm
+    return {
+        "norm": nrm,
+        "mu": (ekin + etrap + 2.0 * ec + 2.0 * edd) / nrm,
+        "energy": (ekin + etrap + ec + edd) / nrm,
+        "e_kin": ekin, "e_trap": etrap, "e_contact": ec, "e_dd": edd,
+        "rms": (np.sqrt(ma), np.sqrt(mb), np.sqrt(ma + mb)),
+    }

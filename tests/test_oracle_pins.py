@@ -435,6 +435,114 @@ def test_ground_state_driver_interacting_virial():
 
 
 # ---------------------------------------------------------------------------
+# Quasi-two-dimensional programs
+# ---------------------------------------------------------------------------
+
+def _q2d(n=(32, 48), d=(0.3, 0.25), dt=0.004, trap=(1.0, 1.3), nu_t=8.0, g=20.0, gd=6.0, imag=True,
+         dipoles="perp"):
+    return O.Params2D(tuple(n), tuple(d), dt, tuple(trap), nu_t, g, gd, imag, dipoles)
+
+
+@pytest.mark.parametrize("dipoles", ["perp", "inplane"])
+def test_q2d_kernel_is_the_tight_axis_average_of_the_3d_kernel(dipoles):
+    """U2(q) against direct quadrature of int dk_t/(2 pi) U(q, k_t)
+    exp(-k_t^2 l^2/2) with the 3D kernel (4 pi/3)(3 cos^2 - 1) of dipoles along
+    the tight axis or along the plane's axis b."""
+    p = _q2d(nu_t=5.0, dipoles=dipoles)
+    U2 = O.q2d_kernel(p)
+    qa = 2 * np.pi * np.fft.fftfreq(p.n[0], d=p.d[0])
+    qb = 2 * np.pi * np.fft.rfftfreq(p.n[1], d=p.d[1])
+    ell = 1 / math.sqrt(p.nu_t)
+    for ia, ib in [(1, 0), (0, 1), (3, 5), (7, 2), (16, 24), (5, 0), (0, 20)]:
+        q2 = qa[ia] ** 2 + qb[ib] ** 2
+
+        def f(kt):
+            k2 = q2 + kt * kt
+            c2 = kt * kt / k2 if dipoles == "perp" else qb[ib] ** 2 / k2
+            return (4 * np.pi / 3) * (3 * c2 - 1) * math.exp(-kt * kt * ell * ell / 2) / (2 * np.pi)
+        val = 2 * integrate.quad(f, 0, np.inf, epsabs=1e-13, epsrel=1e-12, limit=400)[0]
+        assert abs(U2[ia, ib] - val) < 1e-9 * max(1.0, abs(val)), (ia, ib, U2[ia, ib], val)
+    # q = 0: (4 pi/3)/(sqrt(2 pi) l) times 2 (perp) or -1 (in plane)
+    pre = (4 * np.pi / 3) / (math.sqrt(2 * np.pi) * ell)
+    assert abs(U2[0, 0] - pre * (2.0 if dipoles == "perp" else -1.0)) < 1e-12 * pre
+
+
+@pytest.mark.parametrize("dipoles,sa,sb", [("perp", 1.1, 1.1), ("perp", 0.7, 0.7), ("inplane", None, 1.6),
+                                            ("inplane", None, 0.6)])
+def test_q2d_dipolar_energy_of_gaussian_equals_the_3d_closed_form(dipoles, sa, sb):
+    """The quasi-2D state psi(a, b) phi(t) of a Gaussian in the plane is a 3D
+    Gaussian; when it is axially symmetric about the dipole axis its dipolar
+    energy has the closed form of the 3D pin (gd = 1, unit norm, no cut-off).
+    perp: axis t, widths (sigma_rho, l); in plane: axis b, sigma_a = l.  The
+    periodic plane adds the images' 1/r^3 tail, so the grid value approaches
+    the closed form as L^-3: eightfold per doubling of the box."""
+    nu_t = 4.0
+    ell = 1 / math.sqrt(nu_t)
+    if dipoles == "inplane":
+        sa = ell
+    ref = _edd_gaussian_closed(sa, ell) if dipoles == "perp" else _edd_gaussian_closed(ell, sb)
+    errs = []
+    for n in (320, 640, 1280):  # L = 28.8, 57.6, 115.2
+        p = _q2d(n=(n, n), d=(0.09, 0.09), nu_t=nu_t, g=0.0, gd=1.0, dipoles=dipoles)
+        xa, xb = O.q2d_grid(p)
+        dens = np.exp(-(xa[:, None] / sa) ** 2 - (xb[None, :] / sb) ** 2)
+        dens /= np.sum(dens) * p.dA
+        errs.append(abs(O.q2d_observables(p, np.sqrt(dens).astype(complex))["e_dd"] - ref) / abs(ref))
+    assert errs[-1] < 3e-5, errs
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 6.5 < e0 / e1 < 9.5, errs
+
+
+def test_q2d_contact_coupling_is_the_tight_axis_average():
+    """E_c of psi(a, b) equals the 3D contact energy g/2 int |psi phi|^4 of the
+    product state, with phi the tight trap's ground state sampled on a fine
+    grid along t."""
+    p = _q2d(n=(24, 30), d=(0.35, 0.3), nu_t=6.0, g=17.0, gd=0.0)
+    psi = W.random_state((p.n[0], 1, p.n[1]), (p.d[0], 1.0, p.d[1]), seed=41)[:, 0, :]
+    ec2 = O.q2d_observables(p, psi)["e_contact"]
+    t = np.linspace(-6, 6, 4001)
+    dt_ = t[1] - t[0]
+    phi2 = np.exp(-t ** 2 * p.nu_t) * math.sqrt(p.nu_t / np.pi)  # |phi|^2, unit norm
+    ec3 = 0.5 * p.g * float(np.sum(np.abs(psi) ** 4) * p.dA) * float(np.sum(phi2 ** 2) * dt_)
+    assert abs(ec2 - ec3) < 1e-9 * ec3
+
+
+@pytest.mark.parametrize("imag", [False, True])
+def test_q2d_noninteracting_step_is_exactly_separable(imag):
+    p = _q2d(n=(12, 14), d=(0.4, 0.35), dt=0.02, trap=(1.0, 1.7), g=0.0, gd=0.0, imag=imag)
+    rng = np.random.default_rng(42)
+    f = [rng.normal(size=p.n[a]) + 1j * rng.normal(size=p.n[a]) for a in range(2)]
+    psi0 = np.einsum("i,j->ij", *f)
+    steps = 12
+    got = O.q2d_evolve(p, psi0, steps)
+    p3 = _params((p.n[0], p.n[1], 4), (p.d[0], p.d[1], 1.0), dt=p.dt, trap=(p.trap[0], p.trap[1], 0.0),
+                 imag=imag)
+    g = [np.linalg.matrix_power(_axis_transfer(p3, a), steps) @ f[a] for a in range(2)]
+    ref = np.einsum("i,j->ij", *g)
+    if imag:
+        ref = ref / math.sqrt(np.sum(np.abs(ref) ** 2) * p.dA)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dipoles", ["perp", "inplane"])
+def test_q2d_real_time_conserves_norm_and_reverses(dipoles):
+    p = _q2d(n=(20, 24), d=(0.35, 0.3), dt=0.004, g=25.0, gd=10.0, imag=False, dipoles=dipoles)
+    back = _q2d(n=(20, 24), d=(0.35, 0.3), dt=-0.004, g=25.0, gd=10.0, imag=False, dipoles=dipoles)
+    psi0 = W.random_state((p.n[0], 1, p.n[1]), (p.d[0], 1.0, p.d[1]), seed=43)[:, 0, :]
+    psi = O.q2d_evolve(p, psi0, 20)
+    n0 = np.sum(np.abs(psi0) ** 2)
+    assert abs(np.sum(np.abs(psi) ** 2) - n0) < 1e-13 * n0
+    for _ in range(20):  # the inverse step: sweeps with -dt, then the phase with -dt
+        for axis in (1, 0):
+            c = back.dt / (4.0 * back.d[axis] ** 2)
+            psi = O.cn_solve_axis(psi, 1j * c, axis)
+        dens = np.abs(psi) ** 2
+        th = back.dt * (O.q2d_trap(back) + back.g2 * dens + back.gd * O.q2d_potential(back, dens))
+        psi = psi * np.exp(-1j * th)
+    assert np.max(np.abs(psi - psi0)) < 1e-12 * np.max(np.abs(psi0))
+
+
+# ---------------------------------------------------------------------------
 # Adjoint
 # ---------------------------------------------------------------------------
 
