@@ -66,11 +66,30 @@ typedef enum {
     DGPE_ESTATE = 6              /* the call does not fit the plan's mode        */
 } dgpe_status;
 
-/* mode = time | precision */
+/* mode = time | precision [| quasi-2D] */
 #define DGPE_IMAG 0u
 #define DGPE_REAL 1u
 #define DGPE_F64 0u
 #define DGPE_F32 2u
+/* Quasi-two-dimensional plans (the paper's 2d programs: the GPE in two spatial
+ * dimensions, "Nature of problem"): the grid is (N1, 1, N2) and its middle axis
+ * is a tight harmonic trap of frequency trap[1] whose ground state
+ * phi(t) = exp(-t^2/(2 l^2))/(pi l^2)^(1/4), l = 1/sqrt(trap[1]), is integrated
+ * out.  The plane's equation has the contact coupling g/(sqrt(2 pi) l) and the
+ * dipolar kernel of the 3D one averaged over phi^2 along the tight axis (no
+ * cut-off; u = q l/sqrt 2, F(u) = sqrt(pi) u exp(u^2) erfc(u)):
+ *   DGPE_Q2D_PERP     dipoles along the tight axis (the XY programs):
+ *                     U(q) = (4 pi/3)/(sqrt(2 pi) l) (2 - 3 F(u))
+ *   DGPE_Q2D_INPLANE  dipoles along the plane's second axis (z; the XZ
+ *                     programs): U(q) = (4 pi/3)/(sqrt(2 pi) l)(-1 + 3 qz^2/q^2 F(u))
+ * g and gd are the 3D couplings; d[1] is ignored (dV = d[0] d[2]); the trap is
+ * a/2 (nu^2 x^2 + gamma^2 z^2) in the plane, and reported energies leave out
+ * the tight axis' constant trap[1]/2 (no kinetic term along it; rms[1] = 0,
+ * rms[3] the in-plane radius).  No y transforms and no y sweep run; the
+ * adjoint is not available.  Changing TRAP_LAMBDA rebuilds the kernel table
+ * (synchronous). */
+#define DGPE_Q2D_PERP 4u
+#define DGPE_Q2D_INPLANE 8u
 
 /* dgpe_plan_set parameters */
 #define DGPE_PARAM_G 0
@@ -85,7 +104,8 @@ typedef enum {
                                   in 16-line segments and pass 5 joins them (see the pass list); 0: the
                                   separate y sweep.  Same result to rounding either way */
 #define DGPE_PARAM_SCHEME 9    /* 0 (default): the first-order (Lie) step of the paper's method;
-                                  1: the symmetric (Strang) step, see dgpe_step */
+                                  1: the symmetric (Strang) step, see dgpe_step (3D plans only:
+                                  DGPE_ESTATE for quasi-2D ones) */
 
 /* adjoint objectives */
 #define DGPE_OBJ_ENERGY 0
@@ -109,13 +129,14 @@ typedef struct {
 size_t dgpe_workspace_bytes(const int32_t n[3], uint32_t mode);
 
 /* Create a plan.
- *   n[3]        Nx, Ny, Nz (each even, 2^a 3^b, 4..1024)
+ *   n[3]        Nx, Ny, Nz (each even, 2^a 3^b, 4..1024; Ny = 1 for quasi-2D)
  *   d[3]        grid spacings > 0
  *   dt          time step > 0
  *   trap[3]     nu, lambda, gamma (trap frequencies along x, y, z), finite
  *   g, gd       contact and dipolar strengths, finite
- *   cutoff_R    kernel cut-off radius; <= 0 selects min(N_i d_i)/2
- *   mode        DGPE_IMAG | DGPE_REAL, combined with DGPE_F64 | DGPE_F32
+ *   cutoff_R    kernel cut-off radius; <= 0 selects min(N_i d_i)/2 (3D only)
+ *   mode        DGPE_IMAG | DGPE_REAL, combined with DGPE_F64 | DGPE_F32 and
+ *               optionally DGPE_Q2D_PERP or DGPE_Q2D_INPLANE
  *   workspace   device buffer of workspace_bytes >= dgpe_workspace_bytes()
  *   hip_stream  hipStream_t for all work (NULL: the default stream)
  * Fills the workspace's constant tables (dipolar kernel, twiddles, Thomas

@@ -30,9 +30,10 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def workspace_bytes(n, real_time=False, f32=False):
+def workspace_bytes(n, real_time=False, f32=False, q2d=None):
     n_arr = (ctypes.c_int32 * 3)(*n)
-    mode = (_lib.DGPE_REAL if real_time else _lib.DGPE_IMAG) | (_lib.DGPE_F32 if f32 else _lib.DGPE_F64)
+    mode = ((_lib.DGPE_REAL if real_time else _lib.DGPE_IMAG) | (_lib.DGPE_F32 if f32 else _lib.DGPE_F64)
+            | _lib.Q2D[q2d])
     return int(load().dgpe_workspace_bytes(n_arr, mode))
 
 
@@ -47,10 +48,13 @@ class Plan:
     noalloc   True: no workspace tensor; the plan uses the library's static
               device scratch (dgpe_plan_create_noalloc, at most 64 MiB; a later
               such plan on the same device supersedes this one)
+    q2d       None (3D), or "perp" / "inplane" for a quasi-2D plan on an
+              (N1, 1, N2) grid whose middle axis is the tight trap trap[1]
+              (dipoles along the tight axis, or along z in the plane)
     """
 
     def __init__(self, n, d, dt, trap, g, gd, cutoff=0.0, real_time=False, dtype=None,
-                 device="cuda", stream=None, noalloc=False):
+                 device="cuda", stream=None, noalloc=False, q2d=None):
         torch = _torch()
         dtype = torch.complex128 if dtype is None else dtype
         if dtype not in (torch.complex128, torch.complex64):
@@ -68,7 +72,9 @@ class Plan:
         if self.device.type == "cuda" and self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         f32 = dtype == torch.complex64
-        self.mode = (_lib.DGPE_REAL if real_time else _lib.DGPE_IMAG) | (_lib.DGPE_F32 if f32 else _lib.DGPE_F64)
+        self.q2d = q2d
+        self.mode = ((_lib.DGPE_REAL if real_time else _lib.DGPE_IMAG) | (_lib.DGPE_F32 if f32 else _lib.DGPE_F64)
+                     | _lib.Q2D[q2d])
         n_arr = (ctypes.c_int32 * 3)(*self.n)
         nbytes = int(self.lib.dgpe_workspace_bytes(n_arr, self.mode))
         if nbytes == 0:

@@ -24,6 +24,7 @@ STATUS_NAMES = {
     4: "DGPE_EHIP", 5: "DGPE_ENONFINITE", 6: "DGPE_ESTATE",
 }
 DGPE_IMAG, DGPE_REAL, DGPE_F64, DGPE_F32 = 0, 1, 0, 2
+Q2D = {None: 0, "perp": 4, "inplane": 8}  # DGPE_Q2D_PERP, DGPE_Q2D_INPLANE
 PARAM = {"g": 0, "gd": 1, "nu": 2, "lambda": 3, "gamma": 4, "dt": 5, "real_time": 6, "fast_fft": 7,
          "fused_y": 8, "scheme": 9}
 SCHEME = {"lie": 0, "strang": 1}

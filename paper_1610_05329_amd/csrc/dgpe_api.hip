@@ -50,6 +50,16 @@ constexpr size_t kLdsBudget = 64 * 1024;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
+// a quasi-2D plan's grid is (N1, 1, N2): the middle axis is the tight one
+bool q2d_mode(uint32_t mode) { return (mode & (DGPE_Q2D_PERP | DGPE_Q2D_INPLANE)) != 0; }
+
+bool size_ok(int n);
+
+bool grid_ok(const int32_t n[3], uint32_t mode) {
+    if (q2d_mode(mode)) return n[1] == 1 && size_ok(n[0]) && size_ok(n[2]);
+    return size_ok(n[0]) && size_ok(n[1]) && size_ok(n[2]);
+}
+
 bool size_ok(int n) {
     if (n < 4 || n > 1024 || (n & 1)) return false;
     while (n % 2 == 0) n /= 2;
@@ -285,12 +295,16 @@ dgpe_status check_ptr(const void* ptr, const char* what) {
 
 // ---- the time loop ---------------------------------------------------------
 
+// A grid with one point along y (the quasi-2D plans) has no y transform and
+// no y sweep.
+bool has_y(const Plan& p) { return p.n[1] > 1; }
+
 template <typename T>
 dgpe_status convolve_density(Plan& p, const void* psi, const double* sigma) {
     DGPE_HIP(launch_r2c_density<T>(p, psi, sigma));
-    DGPE_HIP(launch_rows<T>(p, false));
+    if (has_y(p)) DGPE_HIP(launch_rows<T>(p, false));
     DGPE_HIP(launch_xmul<T>(p));
-    DGPE_HIP(launch_rows<T>(p, true));
+    if (has_y(p)) DGPE_HIP(launch_rows<T>(p, true));
     return DGPE_OK;
 }
 
@@ -376,14 +390,14 @@ dgpe_status run_steps_strang(Plan& p, void* psi, int nsteps, const double* amp, 
         const bool merged = !p.imag && s > 0;
         const double a_nl = merged ? 0.5 * ((amp ? amp[s - 1] : 1.0) + a) : a;
         DGPE_PASS(t, 0, (launch_r2c_density<T>(p, psi, sg)));
-        DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
+        if (has_y(p)) DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
         DGPE_PASS(t, 2, (launch_xmul<T>(p)));
-        DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
+        if (has_y(p)) DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
         {
             NonlinearStep half(p, merged ? p.dt : 0.5 * p.dt);
             DGPE_PASS(t, 4, (launch_c2r_step<T>(p, psi, psi, sg, a_nl)));
         }
-        DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
+        if (has_y(p)) DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
         DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, nullptr)));
         if (p.imag || s + 1 == nsteps) {  // the trailing half as a pass of its own
             dgpe_status st = convolve_density<T>(p, psi, nullptr);
@@ -422,10 +436,10 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
         DGPE_PASS(t, 0, (launch_r2c_density<T>(p, src, fold ? nullptr : sg)));
         if (fold && sg)
             DGPE_PASS(t, 1, (launch_rows<T>(p, false, p.red, nb_x, sigma)));
-        else
+        else if (has_y(p))
             DGPE_PASS(t, 1, (launch_rows<T>(p, false)));
         DGPE_PASS(t, 2, (launch_xmul<T>(p)));
-        DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
+        if (has_y(p)) DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
         if (car && !phs) {
             DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, nullptr, car, fold && sg)));
             DGPE_PASS(t, 5, (launch_cn_ycarry<T>(p, car)));
@@ -433,7 +447,7 @@ dgpe_status run_steps(Plan& p, void* psi, int nsteps, const double* amp, PassTim
                                                   (char*)car + 3 * car_bytes)));
         } else {
             DGPE_PASS(t, 4, (launch_c2r_step<T>(p, src, psi, sg, a, phs)));
-            DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
+            if (has_y(p)) DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
             DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, p.imag ? p.red : nullptr)));
         }
         if (p.imag && (!fold || s + 1 == nsteps))
@@ -456,6 +470,7 @@ void pass_bytes(const Plan& p, double b[DGPE_NPASS]) {
     b[4] = spec + 2.0 * state;   // read S and psi, write psi
     b[5] = 2.0 * state;          // psi in place
     b[6] = 2.0 * state;
+    if (!has_y(p)) b[1] = b[3] = b[5] = 0.0;  // no y passes
     if (fused_y(p)) {
         const bool fold = p.f32 ? use_folded_norm<float>(p) : use_folded_norm<double>(p);
         if (fold) b[1] += 8.0 * cn_strided_blocks(p, 0, true);  // the norm partials
@@ -480,8 +495,9 @@ dgpe_status observables_impl(Plan& p, const void* psi, double amp, dgpe_obs* out
     DGPE_HIP(hipStreamSynchronize(p.stream));
     const double dV = p.d[0] * p.d[1] * p.d[2];
     const double nrm = h[0] * dV;
-    const double ekin =
-        0.5 * (h[1] / (p.d[0] * p.d[0]) + h[2] / (p.d[1] * p.d[1]) + h[3] / (p.d[2] * p.d[2])) * dV;
+    // (a quasi-2D plan has no kinetic energy along its tight axis)
+    const double ky = p.q2d ? 0.0 : h[2] / (p.d[1] * p.d[1]);
+    const double ekin = 0.5 * (h[1] / (p.d[0] * p.d[0]) + ky + h[3] / (p.d[2] * p.d[2])) * dV;
     const double etrap = amp * h[4] * dV;
     const double ec = 0.5 * p.g * h[5] * dV;
     const double edd = 0.5 * p.gd * h[6] * dV;
@@ -652,9 +668,14 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
 dgpe_status check_plan_args(const int32_t n[3], const double d[3], double dt, const double trap[3],
                             double g, double gd, double cutoff_R, uint32_t mode) {
     if (!n || !d || !trap) return fail(DGPE_EINVAL, "n, d and trap must be non-NULL");
-    if (mode & ~(DGPE_REAL | DGPE_F32)) return fail(DGPE_EINVAL, "unknown mode bits");
+    if (mode & ~(DGPE_REAL | DGPE_F32 | DGPE_Q2D_PERP | DGPE_Q2D_INPLANE))
+        return fail(DGPE_EINVAL, "unknown mode bits");
+    if ((mode & DGPE_Q2D_PERP) && (mode & DGPE_Q2D_INPLANE))
+        return fail(DGPE_EINVAL, "DGPE_Q2D_PERP and DGPE_Q2D_INPLANE exclude each other");
+    if (q2d_mode(mode) && n[1] != 1)
+        return fail(DGPE_EUNSUPPORTED_SIZE, "a quasi-2D grid is (N1, 1, N2)");
     for (int a = 0; a < 3; ++a)
-        if (!size_ok(n[a]))
+        if (!(q2d_mode(mode) && a == 1) && !size_ok(n[a]))
             return fail(DGPE_EUNSUPPORTED_SIZE,
                         "grid size " + std::to_string(n[a]) +
                             " must be even, of the form 2^a 3^b, and in [4, 1024]");
@@ -663,6 +684,8 @@ dgpe_status check_plan_args(const int32_t n[3], const double d[3], double dt, co
     if (!(dt > 0) || !std::isfinite(dt)) return fail(DGPE_EINVAL, "dt must be finite and > 0");
     if (!finite3(trap) || !std::isfinite(g) || !std::isfinite(gd) || !std::isfinite(cutoff_R))
         return fail(DGPE_EINVAL, "trap, g, gd and cutoff must be finite");
+    if (q2d_mode(mode) && !(trap[1] > 0))
+        return fail(DGPE_EINVAL, "a quasi-2D plan needs the tight trap frequency trap[1] > 0");
     return DGPE_OK;
 }
 
@@ -673,6 +696,12 @@ constexpr int kMaxDevices = 64;
 std::atomic<uint64_t> g_scratch_gen[kMaxDevices];
 std::mutex g_scratch_mu;
 void* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each device
+
+// Contact coupling the kernels use: g, or for a quasi-2D plan g int phi^4 =
+// g / (sqrt(2 pi) l) over the tight trap's ground state phi, l = 1/sqrt(trap[1]).
+double contact_coupling(const Plan& p) {
+    return p.q2d ? p.g_in * std::sqrt(p.trap[1] / (2.0 * M_PI)) : p.g_in;
+}
 
 dgpe_status create_plan(dgpe_plan* out, const int32_t n[3], const double d[3], double dt,
                         const double trap[3], double g, double gd, double cutoff_R, uint32_t mode,
@@ -702,9 +731,14 @@ dgpe_status create_plan(dgpe_plan* out, const int32_t n[3], const double d[3], d
     p->dt = dt;
     p->dt_nl = dt;
     p->scheme = 0;
-    p->g = g;
+    p->q2d = (mode & DGPE_Q2D_PERP) ? 1 : (mode & DGPE_Q2D_INPLANE) ? 2 : 0;
+    if (p->q2d) p->d[1] = 1.0;  // no spacing along the tight axis: dV = d1 d2
+    p->g_in = g;
+    p->g = contact_coupling(*p);
     p->gd = gd;
-    p->R = cutoff_R > 0 ? cutoff_R : 0.5 * std::min({n[0] * d[0], n[1] * d[1], n[2] * d[2]});
+    p->R = cutoff_R > 0 ? cutoff_R
+           : p->q2d   ? 0.5 * std::min(n[0] * d[0], n[2] * d[2])
+                      : 0.5 * std::min({n[0] * d[0], n[1] * d[1], n[2] * d[2]});
     p->imag = (mode & DGPE_REAL) == 0;
     p->f32 = f32;
     p->stream = stream;
@@ -792,8 +826,9 @@ const char* dgpe_last_error(void) { return g_last_error.c_str(); }
 size_t dgpe_workspace_bytes(const int32_t n[3], uint32_t mode) {
     if (!n) return 0;
     int nn[3] = {n[0], n[1], n[2]};
-    for (int a = 0; a < 3; ++a)
-        if (!size_ok(nn[a])) return 0;
+    if (mode & ~(DGPE_REAL | DGPE_F32 | DGPE_Q2D_PERP | DGPE_Q2D_INPLANE)) return 0;
+    if ((mode & DGPE_Q2D_PERP) && (mode & DGPE_Q2D_INPLANE)) return 0;
+    if (!grid_ok(n, mode)) return 0;
     size_t offs[OFF_END + 1];
     if (!layout(nn, (mode & DGPE_F32) != 0, offs, nullptr)) return 0;
     return offs[OFF_END];
@@ -839,10 +874,25 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
     if (!std::isfinite(value)) return fail(DGPE_EINVAL, "value must be finite");
     Plan& p = *plan;
     switch (param) {
-        case DGPE_PARAM_G: p.g = value; return DGPE_OK;
+        case DGPE_PARAM_G:
+            p.g_in = value;
+            p.g = contact_coupling(p);
+            return DGPE_OK;
         case DGPE_PARAM_GD: p.gd = value; return DGPE_OK;
         case DGPE_PARAM_TRAP_NU: p.trap[0] = value; return DGPE_OK;
-        case DGPE_PARAM_TRAP_LAMBDA: p.trap[1] = value; return DGPE_OK;
+        case DGPE_PARAM_TRAP_LAMBDA:
+            if (!p.q2d) {
+                p.trap[1] = value;
+                return DGPE_OK;
+            }
+            // quasi-2D: the tight axis sets the contact coupling and the kernel
+            if (!(value > 0)) return fail(DGPE_EINVAL, "the tight trap frequency must be > 0");
+            p.trap[1] = value;
+            p.g = contact_coupling(p);
+            DGPE_HIP(hipStreamSynchronize(p.stream));
+            DGPE_HIP(p.f32 ? launch_ukern<float>(p) : launch_ukern<double>(p));
+            DGPE_HIP(hipStreamSynchronize(p.stream));
+            return DGPE_OK;
         case DGPE_PARAM_TRAP_GAMMA: p.trap[2] = value; return DGPE_OK;
         case DGPE_PARAM_FAST_FFT:
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "FAST_FFT takes 0 or 1");
@@ -854,6 +904,8 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
             return DGPE_OK;
         case DGPE_PARAM_SCHEME:
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "SCHEME takes 0 or 1");
+            if (value == 1.0 && p.q2d)
+                return fail(DGPE_ESTATE, "the symmetric step is for three-dimensional plans");
             p.scheme = (int)value;
             return DGPE_OK;
         case DGPE_PARAM_DT:
@@ -1032,6 +1084,7 @@ dgpe_status dgpe_step_adjoint(dgpe_plan plan, const void* psi0, int32_t nsteps, 
     Plan& p = *plan;
     if (p.imag) return fail(DGPE_ESTATE, "the adjoint needs a real-time plan");
     if (p.scheme != 0) return fail(DGPE_ESTATE, "the adjoint is that of the first-order step");
+    if (p.q2d) return fail(DGPE_ESTATE, "the adjoint is that of the three-dimensional step");
     if (nsteps < 1 || ckpt_every < 1) return fail(DGPE_EINVAL, "nsteps and ckpt_every must be >= 1");
     if (!amp || !J || !dJ_damp || !dJ_dtrap) return fail(DGPE_EINVAL, "amp, J, dJ_damp, dJ_dtrap required");
     for (int i = 0; i <= nsteps; ++i)

@@ -48,6 +48,9 @@ struct Plan {
     double dt_nl;  // time step of the nonlinear phase in the fused z pass (dt, or dt/2
                    // in the first step of the symmetric scheme)
     int scheme;    // 0: first-order (Lie) step; 1: symmetric (Strang) step
+    int q2d;       // 0: 3D; quasi-2D on an (N1, 1, N2) grid with dipoles along the
+                   // tight axis (1) or along the plane's second axis (2)
+    double g_in;   // the caller's contact coupling (g holds the one the kernels use)
     double trap[3];
     double g, gd, R;
     bool imag, f32;

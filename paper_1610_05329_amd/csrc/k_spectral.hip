@@ -472,6 +472,28 @@ __global__ void __launch_bounds__(256) k_c2r_phi(T* __restrict__ phi, const cx<T
 }
 
 // U_R(k)/Nt on the table [kz][|kx|][ky] (plan time), FP64 math.
+// Quasi-2D kernel / Nt on the table [kz][|kx|] (the grid's y axis is the
+// tight one, of one point): the 3D kernel of dipoles along the tight axis
+// (perp) or along z averaged over the tight trap's ground state of width l,
+//   perp:     (4 pi/3)/(sqrt(2 pi) l) (2 - 3 F(u))
+//   in plane: (4 pi/3)/(sqrt(2 pi) l) (-1 + 3 (kz^2/q^2) F(u)),
+// u = q l / sqrt 2, F(u) = sqrt(pi) u exp(u^2) erfc(u) (erfcx: no overflow).
+template <typename T>
+__global__ void k_ukern_q2d(T* __restrict__ out, int Nx, int Nz, double dkx, double dkz, double ell,
+                            bool perp, double inv_nt) {
+    const int hx = Nx / 2 + 1, hz = Nz / 2 + 1;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= hx * hz) return;
+    const int kx = i % hx, kz = i / hx;
+    const double qx = kx * dkx, qz = kz * dkz;
+    const double q2 = qx * qx + qz * qz;
+    const double u = sqrt(q2) * ell * M_SQRT1_2;
+    const double F = 1.7724538509055160273 * u * erfcx(u);  // sqrt(pi) u erfcx(u)
+    const double pre = (4.0 * M_PI / 3.0) / (2.5066282746310005024 * ell);  // / (sqrt(2 pi) l)
+    const double v = perp ? pre * (2.0 - 3.0 * F) : pre * (-1.0 + (q2 > 0.0 ? 3.0 * qz * qz / q2 * F : 0.0));
+    out[i] = T(v * inv_nt);
+}
+
 template <typename T>
 __global__ void k_ukern(T* __restrict__ out, int Nx, int Ny, int Nz, double dkx, double dky,
                         double dkz, double R, double inv_nt) {
@@ -645,6 +667,15 @@ hipError_t launch_c2r_phi(const Plan& p, void* phi_out) {
 template <typename T>
 hipError_t launch_ukern(const Plan& p) {
     const double two_pi = 2.0 * M_PI;
+    if (p.q2d) {
+        const int total = (p.n[0] / 2 + 1) * (p.n[2] / 2 + 1);
+        const double nt = (double)p.n[0] * p.n[2];
+        hipLaunchKernelGGL((k_ukern_q2d<T>), dim3((total + 255) / 256), dim3(256), 0, p.stream,
+                           (T*)p.ukern, p.n[0], p.n[2], two_pi / (p.n[0] * p.d[0]),
+                           two_pi / (p.n[2] * p.d[2]), 1.0 / std::sqrt(p.trap[1]), p.q2d == 1,
+                           1.0 / nt);
+        return hipGetLastError();
+    }
     const double nt = (double)p.n[0] * p.n[1] * p.n[2];
     const size_t total = (size_t)(p.n[0] / 2 + 1) * (p.n[1] / 2 + 1) * (p.n[2] / 2 + 1);
     const int blocks = (int)std::min<size_t>((total + 255) / 256, 65535);

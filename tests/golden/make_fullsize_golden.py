@@ -5,9 +5,11 @@ oracle and the seeded input module; minutes of CPU time each).
       20 steps from the seeded noisy Gaussian: observables and 512 sampled
       state values.  (These parameters collapse after about 90 steps; the
       record stays on the regular part of the trajectory.)
-  quench_128cubed  128^3: 200 imaginary-time steps at gd = 15 from the trap Gaussian, then
-      the quench gd -> 20 and 1000 real-time steps (dt 0.002): observables at
-      the quench and at the end, and 512 sampled state values.
+  quench_128cubed  128^3: the imaginary-time ground state at gd = 15 from the trap Gaussian
+      (the driver: mu checked every 10 steps, stop when it changes by less
+      than 1e-10 per step, at most 20000 steps), then the quench gd -> 20 and
+      1000 real-time steps (dt 0.002): observables at the quench and at the
+      end, and 512 sampled state values.
   adjoint_96cubed  96^3: 500 imaginary-time steps (dt 0.002, gd 15) from the trap Gaussian
       as psi0, then the adjoint of the final energy through 400 real-time
       steps with the trap amplitude on 40 seeded knots in [0.8, 1.2).
@@ -67,13 +69,16 @@ def make_imag_256cubed():
 
 def make_quench_128cubed():
     cfg = W.CONFIGS["quench_128cubed"]
-    prep_steps, steps = 200, 1000
+    tol, cap, every, steps = 1e-10, 20000, 10, 1000
     prep = O.Params.from_config(cfg, gd=15.0, imag=True)
-    psi = O.evolve(prep, W.gaussian_state(cfg.n, cfg.d, cfg.trap), prep_steps)
+    psi, prep_steps, rate, mu = O.ground_state(prep, W.gaussian_state(cfg.n, cfg.d, cfg.trap), tol, cap,
+                                               every)
     p = O.Params.from_config(cfg, imag=False)
     o0 = obs(p, psi)
     psi = O.evolve(p, psi, steps)
-    return {"config": "quench_128cubed", "prep_imag_steps": prep_steps, "prep_gd": 15.0, "steps": steps,
+    return {"config": "quench_128cubed", "prep": "ground_state", "prep_tol": tol, "prep_max_steps": cap,
+            "prep_check_every": every, "prep_imag_steps": prep_steps, "prep_dmu_per_step": rate,
+            "prep_mu": mu, "prep_gd": 15.0, "steps": steps,
             "observables_start": o0, "observables": obs(p, psi), "samples": samples(psi, 22)}
 
 

@@ -76,7 +76,7 @@ def test_plan_create_validates_before_device_work(lib):
     assert _create(lib, dt=float("nan"))[0] == 1
     assert _create(lib, d=(0.25, -1.0, 0.25))[0] == 1
     assert _create(lib, g=float("inf"))[0] == 1
-    assert _create(lib, mode=8)[0] == 1
+    assert _create(lib, mode=16)[0] == 1  # an unknown mode bit
     assert _create(lib, ws=None)[0] == 3
     assert _create(lib, ws=ctypes.c_void_p(0x1000 + 8), nbytes=1 << 40)[0] == 3
     assert _create(lib, ws=ctypes.c_void_p(0x1000), nbytes=16)[0] == 3
@@ -121,3 +121,25 @@ def test_noalloc_plan_rejects_grids_beyond_its_scratch_before_device_work(lib):
     # the largest grids it serves fit the limit
     assert lib.dgpe_workspace_bytes(_n(128, 128, 128), 0) <= _lib.NOALLOC_MAX_BYTES
     assert lib.dgpe_workspace_bytes(_n(192, 192, 192), 2) <= _lib.NOALLOC_MAX_BYTES
+
+
+def test_quasi2d_mode_validation_before_device_work(lib):
+    """Quasi-2D plans: the grid is (N1, 1, N2), one orientation bit, a positive
+    tight trap frequency; everything else is refused before any HIP call."""
+    PERP, INPLANE = _lib.Q2D["perp"], _lib.Q2D["inplane"]
+    assert lib.dgpe_workspace_bytes(_n(64, 1, 48), PERP) > 0
+    assert lib.dgpe_workspace_bytes(_n(64, 1, 48), INPLANE | 3) > 0
+    assert lib.dgpe_workspace_bytes(_n(64, 1, 48), 0) == 0          # 3D needs Ny >= 4
+    assert lib.dgpe_workspace_bytes(_n(64, 4, 48), PERP) == 0       # quasi-2D needs Ny = 1
+    assert lib.dgpe_workspace_bytes(_n(64, 1, 48), PERP | INPLANE) == 0
+    assert lib.dgpe_workspace_bytes(_n(64, 1, 50), PERP) == 0       # 50 = 2 * 5^2
+
+    def create(n, mode, trap=(1.0, 4.0, 1.0)):
+        h = ctypes.c_void_p()
+        return lib.dgpe_plan_create(ctypes.byref(h), _n(*n), (ctypes.c_double * 3)(0.3, 1.0, 0.3), 0.01,
+                                    (ctypes.c_double * 3)(*trap), 1.0, 1.0, 0.0, mode, None, 0, None)
+    assert create((32, 2, 32), PERP) == 2
+    assert create((32, 1, 32), PERP | INPLANE) == 1
+    assert create((32, 1, 32), PERP, trap=(1.0, 0.0, 1.0)) == 1
+    assert create((32, 1, 32), INPLANE, trap=(1.0, -2.0, 1.0)) == 1
+    assert create((32, 1, 32), PERP) == 3  # valid arguments: then the missing workspace

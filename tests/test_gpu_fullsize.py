@@ -103,21 +103,41 @@ def test_imag_256cubed_whole_grid_matches_oracle(env, imag256_oracle):
     assert l2 < 1e-5
 
 
-def test_quench_128cubed_real_time_matches_oracle_record(env):
-    """128^3: 200 imaginary-time steps at gd = 15, quench to gd = 20, 1000
-    real-time steps, in FP64 and FP32: norm conservation and energy drift per
-    dtype, the record's samples, and whole-grid relative L2 of the FP32 state
-    against the FP64 one (itself within 1e-12 of the oracle at the samples)."""
+@pytest.fixture(scope="module")
+def quench128_ground_state(env):
+    """The 128^3 ground state at gd = 15 from the trap Gaussian by the driver
+    (mu checked every 10 steps, stop below 1e-10 per step), FP64, as the record
+    prepared its own: it must stop at the same step."""
+    torch, dg = env
+    cfg = W.CONFIGS["quench_128cubed"]
+    gold = _golden("quench_128cubed")
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, gold["prep_gd"], dtype=torch.complex128)
+    psi = plan.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
+    out = plan.ground_state(psi, tol=gold["prep_tol"], max_steps=gold["prep_max_steps"],
+                            check_every=gold["prep_check_every"])
+    _say(f"quench_128cubed ground state: {out['steps']} steps (oracle {gold['prep_imag_steps']}), "
+         f"dmu/step {out['dmu_per_step']:.3e} (oracle {gold['prep_dmu_per_step']:.3e}), "
+         f"mu {out['observables']['mu']:.13f} (oracle {gold['prep_mu']:.13f})")
+    assert out["converged"] and out["steps"] == gold["prep_imag_steps"]
+    assert abs(out["observables"]["mu"] - gold["prep_mu"]) < 1e-12 * abs(gold["prep_mu"])
+    host = psi.cpu().numpy()
+    plan.close()
+    return host
+
+
+def test_quench_128cubed_real_time_matches_oracle_record(env, quench128_ground_state):
+    """128^3: the driver's ground state at gd = 15 (FP64), quench to gd = 20,
+    1000 real-time steps in FP64 and FP32 (the FP32 run starts from the same
+    state rounded to FP32): norm conservation and energy drift per dtype, the
+    record's samples, and whole-grid relative L2 of the FP32 state against the
+    FP64 one (itself within 1e-12 of the oracle at the samples)."""
     torch, dg = env
     cfg = W.CONFIGS["quench_128cubed"]
     gold = _golden("quench_128cubed")
     final = {}
     for prec in ("f64", "f32"):
-        plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, gold["prep_gd"], dtype=_dtype(torch, prec))
-        psi = plan.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
-        plan.step(psi, gold["prep_imag_steps"])
-        plan.set("gd", cfg.gd)
-        plan.set("real_time", 1)
+        plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=_dtype(torch, prec))
+        psi = plan.new_state(quench128_ground_state)
         o0 = plan.observables(psi)
         plan.step(psi, gold["steps"])
         o1 = plan.observables(psi)
