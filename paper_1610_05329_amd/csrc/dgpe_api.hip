@@ -143,7 +143,7 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
         // measured at 256^3: 32 columns per block (FP32 recurrences) and 16
         // (FP64 recurrences) overlap loads and solves better than 64
         int zb = narrow ? 32 : 16;
-        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * nseg * (S + 1) + 2 * nseg) * asz; };
+        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * nseg * (S + 1) + 3 * nseg) * asz; };
         while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
         if (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget) return false;
         lc->seg[axis] = S;
@@ -215,7 +215,7 @@ std::vector<T> twiddles(int L, int count) {
 template <typename T>
 std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
     using C = std::complex<long double>;
-    std::vector<C> al(N), P(N), Q(N), E(N), pend(N, C(0)), qbeg(N, C(0));
+    std::vector<C> al(N), P(N), Q(N), E(N), G(N), pend(N, C(0)), qbeg(N, C(0)), H(N, C(0));
     const C diag = C(1) + C(2) * A;
     C m = C(1) / diag;
     for (int i = 0; i < N; ++i) {
@@ -232,6 +232,11 @@ std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
         qbeg[k] = acc;
         acc = 0;
         for (int i = s1 - 1; i >= s0; --i) { acc = P[i] + al[i] * acc; E[i] = acc; }
+        acc = 1;
+        for (int i = s0; i < s1; ++i) { G[i] = acc; acc *= al[i]; }
+        acc = 0;
+        for (int i = s0; i < s1; ++i) acc += G[i] * P[i];
+        H[k] = acc;
     }
     std::vector<T> out(2 * TAB_COUNT * (size_t)N);
     const std::vector<C>* tabs[TAB_COUNT];
@@ -241,6 +246,8 @@ std::vector<T> cn_tables(int N, std::complex<long double> A, int S) {
     tabs[TAB_PEND] = &pend;
     tabs[TAB_QBEG] = &qbeg;
     tabs[TAB_E] = &E;
+    tabs[TAB_G] = &G;
+    tabs[TAB_H] = &H;
     for (int t = 0; t < TAB_COUNT; ++t)
         for (int i = 0; i < N; ++i) {
             out[2 * ((size_t)t * N + i)] = (T)(*tabs[t])[i].real();

@@ -604,7 +604,9 @@ __device__ __forceinline__ cx<A> carry_chain(const cx<A>* buf, const cx<A>* m, i
     return c;
 }
 
-template <typename T, int S, bool RC, bool GUARD, typename TT, typename VS>
+// tg, hs (only for values stored narrower than A): the G table (indexed like
+// ta) and H per segment, see dgpe_internal.h
+template <typename T, int S, bool RC, bool GUARD, typename TT, typename VS, typename TH = double>
 __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
                                                  cx<cn_acc_t<T, RC>> left,
                                                  cx<cn_acc_t<T, RC>> right,
@@ -613,7 +615,9 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
                                                  const cx<cn_acc_t<T, RC>>* pend,
                                                  const cx<cn_acc_t<T, RC>>* qbeg, int tb, int seg,
                                                  int nseg, cx<cn_acc_t<T, RC>>* dl,
-                                                 cx<cn_acc_t<T, RC>>* xf, int line, int nlines) {
+                                                 cx<cn_acc_t<T, RC>>* xf, int line, int nlines,
+                                                 const cx<TT>* tg = nullptr,
+                                                 const cx<TH>* hs = nullptr) {
     using A = cn_acc_t<T, RC>;
     // FP32 recurrences keep the segment's alpha in registers; FP64 ones read it
     // where it is used (register budget)
@@ -629,6 +633,16 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
         if constexpr (kPre) return al[kPre ? i : 0];
         else return widen<A>(ta[tb + i]);
     };
+    // Values stored narrower than the arithmetic (FP32 state, FP64 real-time
+    // recurrences) must be rounded once: storing the zero-carry x and adding
+    // Q_i x_right afterwards rounds those values twice, and that double
+    // rounding drifts the norm (about 6e-6 over 1000 real-time steps at 128^3;
+    // rounding the forward d is harmless).  So the back substitution runs once,
+    // from the true right carry, and the segment's first x from a zero right
+    // carry, which the right carries need, is accumulated in the forward pass
+    // instead: x_first = sum_i G_i d_i = sum_i G_i dloc_i + H c_left.
+    constexpr bool kTwice = sizeof(VS) < sizeof(A);
+    cx<A> xacc = {A(0), A(0)};
     // 1. forward recurrence from a zero carry, with r'_i = u_{i-1} + u_{i+1} +
     // kappa u_i formed on the fly from the input values (threads without a
     // segment read no table)
@@ -644,6 +658,8 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
             if (!GUARD || i < cnt) {
                 dcur = kmul<RC>(alpha(i), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
                 v[i] = to_store<VS>(dcur);
+                // the segment's first x from zero carries on both sides
+                if constexpr (kTwice) xacc = xacc + kmul<RC>(widen<A>(tg[tb + i]), dcur);
             }
             prev = cur;
             cur = nxt;
@@ -651,35 +667,33 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
         dl[seg * nlines + line] = dcur;
     }
     __syncthreads();
-    // Values stored narrower than the arithmetic (FP32 state, FP64 real-time
-    // recurrences) take the back substitution twice: once without stores for
-    // the segment's first value, then from the true right carry, storing each
-    // x once.  Storing the zero-carry x and adding Q_i x_right afterwards
-    // rounds those values twice, and that double rounding drifts the norm
-    // (about 6e-6 over 1000 real-time steps at 128^3); rounding the forward d
-    // does not.
-    constexpr bool kTwice = sizeof(VS) < sizeof(A);
     cx<A> c = {A(0), A(0)};
     if (act) {
         // 2. true d before the segment's first point, from the segments on the
         // left (P correction), then back substitution from a zero carry
         c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
-        cx<A> xcur = {A(0), A(0)};
+        if constexpr (kTwice) {
+            xf[seg * nlines + line] = xacc + kmul<RC>(widen<A>(hs[seg]), c);
+        } else {
+            cx<A> xcur = {A(0), A(0)};
 #pragma unroll
-        for (int i = S - 1; i >= 0; --i) {
-            if (!GUARD || i < cnt) {
-                const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
-                xcur = d + kmul<RC>(alpha(i), xcur);
-                if constexpr (!kTwice) v[i] = to_store<VS>(xcur);
+            for (int i = S - 1; i >= 0; --i) {
+                if (!GUARD || i < cnt) {
+                    const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
+                    xcur = d + kmul<RC>(alpha(i), xcur);
+                    v[i] = to_store<VS>(xcur);
+                }
             }
+            xf[seg * nlines + line] = xcur;
         }
-        xf[seg * nlines + line] = xcur;
     }
     __syncthreads();
     if (act) {
         const cx<A> cr = carry_chain<A, RC, true>(xf, qbeg, seg + 1, nseg, nlines, line);
         if constexpr (kTwice) {
-            // 3. back substitution from the true x after the segment
+            // 3. back substitution from the true x after the segment (the
+            // factors read here, not held since the forward pass)
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             cx<A> xcur = cr;
 #pragma unroll
             for (int i = S - 1; i >= 0; --i) {

@@ -29,7 +29,13 @@ struct FastDiv {
 //   PEND[k] = P at the last point of segment k, QBEG[k] = Q at its first point,
 //   E_i = P_i + alpha_i E_{i+1} (E = 0 past the segment end): the response of
 //   the back substitution to a unit forward carry entering the segment.
-enum { TAB_ALPHA = 0, TAB_P = 1, TAB_Q = 2, TAB_PEND = 3, TAB_QBEG = 4, TAB_E = 5, TAB_COUNT = 6 };
+//   G_i = prod_{j = seg start}^{i - 1} alpha_j (1 at the start): the weight of
+//   d_i in the segment's first x of a back substitution from a zero right
+//   carry, x_first = sum_i G_i d_i; H[k] = sum over segment k of G_i P_i.
+enum {
+    TAB_ALPHA = 0, TAB_P = 1, TAB_Q = 2, TAB_PEND = 3, TAB_QBEG = 4, TAB_E = 5, TAB_G = 6,
+    TAB_H = 7, TAB_COUNT = 8
+};
 
 // Launch parameters of the seven passes for one plan (host side).
 struct Launch {

@@ -22,12 +22,14 @@ struct CnTab {
     const cx<double>* q;
     const cx<double>* pend;
     const cx<double>* qbeg;
+    const cx<double>* g;
+    const cx<double>* h;
 };
 
 CnTab tab_of(const void* base, int N) {
     const cx<double>* t = (const cx<double>*)base;
     return CnTab{t + TAB_ALPHA * N, t + TAB_P * N, t + TAB_Q * N, t + TAB_PEND * N,
-                 t + TAB_QBEG * N};
+                 t + TAB_QBEG * N, t + TAB_G * N, t + TAB_H * N};
 }
 
 template <typename A>
@@ -41,9 +43,9 @@ __device__ __forceinline__ cx<double> tab_at(const cx<double>* t, int i) {
     else return t[i];
 }
 
-// LDS: A1[nseg*ZB] | A2[nseg*ZB] (arithmetic type) | alpha | P | Q (each
+// LDS: A1[nseg*ZB] | A2[nseg*ZB] (arithmetic type) | alpha | P | Q or G (each
 // nseg*(S+1): segment s at s*(S+1), so that the segments of a wave read
-// distinct banks) | pend | qbeg
+// distinct banks) | pend | qbeg | H (per segment; used with G)
 //
 // YC (x axis only): the input is the local solution of the y solve split in
 // 16-line segments, and every value is completed first as
@@ -72,12 +74,14 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     cx<A>* tq = tp + TL;
     cx<A>* pe = tq + TL;
     cx<A>* qb = pe + nseg;
+    cx<A>* hs = qb + nseg;
     // First round of the table loads (one entry of each table per thread,
     // clamped: the writes below are unconditional so the loads stay ahead of
     // the state loads; see tab_stage), then the state, then staging.
     const int i0 = min(tid, L - 1), s0 = min(tid, nseg - 1);
-    // the Q table serves only solves that store at the arithmetic's precision
-    // (a narrower store runs the back substitution twice instead)
+    // solves that store at the arithmetic's precision take the Q table, the
+    // ones that store narrower the G and H tables (see cn_segment_solve); the
+    // tq area holds either
     constexpr bool kQ = sizeof(T) >= sizeof(A);
     const cx<double> a0 = tab_at<RC>(tg.a, i0), p0 = tab_at<RC>(tg.p, i0);
     const cx<double> q0 = kQ ? tab_at<RC>(tg.q, i0) : cx<double>{0.0, 0.0};
@@ -151,18 +155,26 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     }
     ta[i0 + i0 / S] = narrow_tab<A>(a0);
     tp[i0 + i0 / S] = narrow_tab<A>(p0);
-    if constexpr (kQ) tq[i0 + i0 / S] = narrow_tab<A>(q0);
     pe[s0] = narrow_tab<A>(pe0);
     qb[s0] = narrow_tab<A>(qb0);
+    if constexpr (kQ) {
+        tq[i0 + i0 / S] = narrow_tab<A>(q0);
+    } else {
+        // G and H are first read after the neighbour exchange below, which
+        // waits for the state anyway: loaded after it (registers)
+        tq[i0 + i0 / S] = narrow_tab<A>(tab_at<RC>(tg.g, i0));
+        hs[s0] = narrow_tab<A>(tab_at<RC>(tg.h, s0));
+    }
     for (int i = tid + nthr; i < L; i += nthr) {  // lines longer than the block
         const int ip = i + i / S;
         ta[ip] = narrow_tab<A>(tg.a[i]);
         tp[ip] = narrow_tab<A>(tg.p[i]);
-        if constexpr (kQ) tq[ip] = narrow_tab<A>(tg.q[i]);
+        tq[ip] = narrow_tab<A>(kQ ? tg.q[i] : tg.g[i]);
     }
     for (int i = tid + nthr; i < nseg; i += nthr) {
         pe[i] = narrow_tab<A>(tg.pend[i]);
         qb[i] = narrow_tab<A>(tg.qbeg[i]);
+        if constexpr (!kQ) hs[i] = narrow_tab<A>(tg.h[i]);
     }
     cx<T> lastv = v[S - 1];
     if (GUARD) {
@@ -182,7 +194,7 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     }
     __syncthreads();  // neighbour reads done: A2 becomes the forward carries, A1 the backward ones
     cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta, tp, tq, pe, qb, seg * (S + 1), seg,
-                                      nseg, A2, A1, cl, ZB);
+                                      nseg, A2, A1, cl, ZB, tq, hs);
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
@@ -421,7 +433,7 @@ __global__ void __launch_bounds__(256) k_cn_z(cx<T>* __restrict__ f, int Nz, int
         if (e0 + cnt < Nz) right = widen<A>(P[(e0 + cnt) * ES + bl]);
     }
     cn_segment_solve<T, SZ, RC, GUARD>(v, cnt, left, right, kappa, tg.a, tg.p, tg.q, pe, qb, e0,
-                                          seg, nseg, dl, xf, bl, B);
+                                          seg, nseg, dl, xf, bl, B, tg.g, tg.h);
     if (cnt > 0) {
 #pragma unroll
         for (int i = 0; i < SZ; ++i)
@@ -535,7 +547,7 @@ hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
     const cx<double> kappa = {k.re, k.im};
     const int blocks = cn_strided_blocks(p, axis, ycar != nullptr);
     const size_t asz = (p.imag ? sizeof(T) : sizeof(double)) * 2;
-    const size_t sm = (size_t)(2 * threads + 3 * nseg * (S + 1) + 2 * nseg) * asz;
+    const size_t sm = (size_t)(2 * threads + 3 * nseg * (S + 1) + 3 * nseg) * asz;
     const bool guard = (L % S) != 0;
     const cx<double>* ytab = (const cx<double>*)p.cntab[1][0];
 #define DGPE_CN(SV, RCV, GV, YV)                                                                      \
