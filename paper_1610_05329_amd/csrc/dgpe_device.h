@@ -42,12 +42,16 @@ template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.x, -a.y}; }
 template <typename T>
 __device__ __forceinline__ T abs2(cx<T> a) { return a.x * a.x + a.y * a.y; }
-// sin and cos of a phase angle.  Cody-Waite reduction in FP64: k = rint(2x/pi),
-// r = (x - k P1) - k P2 with P1 = pi/2 rounded to 33 significant bits (k P1
-// exact for |k| < 2^20) and P2 = pi/2 - P1; then the Taylor series of sin and
-// cos on |r| <= pi/4 and the quadrant's exchange and signs.  Truncation: the
-// first omitted term is below 2e-9 (FP32: through r^9 and r^10) and below 1e-19
-// (FP64: through r^17 and r^18) relative to the result's scale.
+// sin and cos of a phase angle.  Cody-Waite reduction: k = rint(2x/pi),
+// r = (x - k P1) - k P2 with P2 = pi/2 - P1, then the Taylor series of sin and
+// cos on |r| <= pi/4 and the quadrant's exchange and signs.  FP64: P1 = pi/2
+// rounded to 33 significant bits (k P1 exact for |k| < 2^20).  FP32: P1 = pi/2
+// rounded to FP32 and both steps fused multiply-adds; the first is exact (x and
+// k P1 are multiples of ulp(P1) or of ulp(x) and their difference is below
+// pi/4 + ulp, so it fits 24 bits) and the second rounds once; the omitted
+// tail k (pi/2 - P1 - P2) is below 3e-15 |k|.  Truncation: the first omitted
+// term is below 2e-9 (FP32: through r^9 and r^10) and below 1e-19 (FP64:
+// through r^17 and r^18) relative to the result's scale.
 namespace detail {
 constexpr double kTwoOverPi = 0.6366197723675814;
 constexpr double kPio2Hi = 1.5707963267341256;   // 0x3FF921FB54400000
@@ -69,8 +73,9 @@ __device__ __forceinline__ void quadrant(int q, T sr, T cr, T* s, T* c) {
 }  // namespace detail
 
 __device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
-    int q;
-    const float r = float(detail::reduce_pio2(double(x), &q));
+    const float k = rintf(x * 0.636619772f);
+    const int q = int(k) & 3;
+    const float r = fmaf(-k, -4.37113883e-08f, fmaf(-k, 1.57079637f, x));
     const float r2 = r * r;
     // sin r = r (1 - r^2/3! + r^4/5! - r^6/7! + r^8/9!)
     float ps = 1.0f / 362880.0f;
@@ -439,8 +444,34 @@ struct WaveLines {
         return (c / Nz) * SL + e + (e / SZ) * U;
     }
 
+    // v wider than the state: the values are widened after the rounds, so each
+    // conversion is issued once rather than once per round
     template <typename A>
     __device__ static void to_segments(cx<T>* stg, const cx<T> (&a)[SZ], cx<A> (&v)[SZ], int lane) {
+        if constexpr (std::is_same_v<A, T>) {
+            stage_in(stg, a, v, lane);
+        } else {
+            cx<T> t[SZ];
+            stage_in(stg, a, t, lane);
+#pragma unroll
+            for (int i = 0; i < SZ; ++i) v[i] = widen<A>(t[i]);
+        }
+    }
+
+    template <typename A>
+    __device__ static void store_from_segments(cx<T>* stg, const cx<A> (&v)[SZ], cx<T>* wp,
+                                               int lane) {
+        if constexpr (std::is_same_v<A, T>) {
+            stage_out(stg, v, wp, lane);
+        } else {
+            cx<T> t[SZ];
+#pragma unroll
+            for (int i = 0; i < SZ; ++i) t[i] = cx<T>{T(v[i].x), T(v[i].y)};
+            stage_out(stg, t, wp, lane);
+        }
+    }
+
+    __device__ static void stage_in(cx<T>* stg, const cx<T> (&a)[SZ], cx<T> (&v)[SZ], int lane) {
         const int seg = lane % nseg, sl = lane / nseg;
 #pragma unroll
         for (int r = 0; r < LPW / KR; ++r) {
@@ -454,19 +485,12 @@ struct WaveLines {
             if (sl / KR == r) {
                 const cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
 #pragma unroll
-                for (int j = 0; j < NU; ++j) {
-                    cx<T> t2[U];
-                    load_unit<T>(sp + j * U, t2);
-#pragma unroll
-                    for (int u = 0; u < U; ++u) v[j * U + u] = widen<A>(t2[u]);
-                }
+                for (int j = 0; j < NU; ++j) load_unit<T>(sp + j * U, v + j * U);
             }
         }
     }
 
-    template <typename A>
-    __device__ static void store_from_segments(cx<T>* stg, const cx<A> (&v)[SZ], cx<T>* wp,
-                                               int lane) {
+    __device__ static void stage_out(cx<T>* stg, const cx<T> (&v)[SZ], cx<T>* wp, int lane) {
         const int seg = lane % nseg, sl = lane / nseg;
 #pragma unroll
         for (int r = 0; r < LPW / KR; ++r) {
@@ -474,12 +498,7 @@ struct WaveLines {
             if (sl / KR == r) {
                 cx<T>* sp = stg + (sl - r * KR) * SL + seg * (SZ + U);
 #pragma unroll
-                for (int j = 0; j < NU; ++j) {
-                    cx<T> t2[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) t2[u] = cx<T>{T(v[j * U + u].x), T(v[j * U + u].y)};
-                    store_unit<T>(sp + j * U, t2);
-                }
+                for (int j = 0; j < NU; ++j) store_unit<T>(sp + j * U, v + j * U);
             }
             wave_sync();
 #pragma unroll

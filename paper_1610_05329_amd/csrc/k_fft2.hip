@@ -267,6 +267,14 @@ struct Phys2 {
     double dx, dy, dz, cx, cy, cz;
 };
 
+// Constants of the fused z pass's nonlinear exponent, folded on the host:
+// th = kx ix^2 + ky iy^2 + kz iz^2 + kg sigma |psi|^2 + kd Phi with (ix, iy, iz)
+// the grid offsets from the trap centre, i.e. dt (a V + g sigma |psi|^2 +
+// g_d Phi); all times log2(e) for the FP32 imaginary-time factor (taken as exp2)
+struct NlConst {
+    double kx, ky, kz, kg, kd;
+};
+
 // ADJ: the transformed real field is the adjoint source
 // s = Im(conj(mu) e^{-i theta} psi_n), theta = dt (a V0 + g |psi_n|^2 + g_d Phi_n)
 // (psi holds mu), with the FP64 block sums of s V0, s x^2, s y^2, s z^2 in
@@ -700,7 +708,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
                 const cx<T>* __restrict__ spec, int Nx, int Ny,
                 const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
                 const cx<double>* __restrict__ cntab, cx<double> kappa64,
-                const double* __restrict__ sigma, Phys2 ph,
+                const double* __restrict__ sigma, Phys2 ph, NlConst nl,
                 const cx<double>* __restrict__ ytab, cx<double> kappay64,
                 cx<T>* __restrict__ ycar, int phi_sigma) {
     using A = cn_acc_t<T, RC>;
@@ -790,42 +798,54 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     const int seg = lane % nseg;
     cx<A> v[SZ];
     if (act) {
-    // nonlinear step in the load layout (pre-step density, lazily normalised)
+    // nonlinear step in the load layout (pre-step density, lazily normalised).
+    // The exponent is a line term (x, y) plus a z term, shared by the points
+    // of a line and of a z index, plus the density and Phi terms.  Imaginary
+    // time, FP32: the factor sqrt(sigma) enters the exponent; its rounding only
+    // rescales the stored state, which the next step's norm absorbs.  Real
+    // time takes no sigma (the phase keeps the norm).
+    constexpr bool kB2 = RC && sizeof(T) == 4;
     const double sg = sigma ? sigma[0] : 1.0;
-    const T sig = T(sg), rs = T(sqrt(sg));
-    // phi_sigma: the spectrum is of the unscaled density (sigma applied here)
-    const T phs = phi_sigma ? sig : T(1);
-    const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
-    const T xx = T(x - ph.hx) * T(ph.dx);
-    const T vx = T(ph.cx) * xx * xx;
+    const T kn = T(nl.kg * sg), kp = T(phi_sigma ? nl.kd * sg : nl.kd);
+    const T ky = T(nl.ky), kz = T(nl.kz);
+    const int ix = x - ph.hx;
+    T cx0 = T(nl.kx * double(ix * ix));
+    if constexpr (kB2) cx0 -= T(0.5) * __builtin_amdgcn_logf(T(sg));
+    [[maybe_unused]] const T rs = RC && !kB2 ? T(sqrt(sg)) : T(1);
+    const int iy0 = y0 + wv * LPW - ph.hy;
     const cx<T>* prow = reg + wv * LPW * PS;
+    // with 64 U | Nz the units j of all lanes lie on one line and the z offset
+    // of a unit is a constant plus lane U
+    constexpr bool kLine = Nz % (64 * U) == 0;
 #pragma unroll
     for (int j = 0; j < NU; ++j) {
         const int c0 = (j * 64 + lane) * U;
-        const int lw = c0 / Nz, e0 = c0 % Nz;
-        const T yy = T(y0 + wv * LPW + lw - ph.hy) * T(ph.dy);
-        const T vxy = vx + T(ph.cy) * yy * yy;
+        const int lw = kLine ? (j * 64 * U) / Nz : c0 / Nz;
+        const int e0 = kLine ? (j * 64 * U) % Nz + lane * U : c0 % Nz;
+        const int iy = iy0 + lw;
+        const T cl = ky * T(iy * iy) + cx0;
         const int m = e0 >> 1;
-        const cx<T> fv = phs * prow[lw * PS + m + (m >> 3)];
+        const cx<T> fv = prow[lw * PS + m + (m >> 3)];
         if constexpr (PHI) {  // Phi of the pre-step density, for the adjoint
-            if constexpr (U == 2) *reinterpret_cast<cx<T>*>(phi_out + wl + c0) = fv;
-            else phi_out[wl + c0] = (e0 & 1) ? fv.y : fv.x;
+            const T phs = phi_sigma ? T(sg) : T(1);
+            if constexpr (U == 2) *reinterpret_cast<cx<T>*>(phi_out + wl + c0) = phs * fv;
+            else phi_out[wl + c0] = phs * ((e0 & 1) ? fv.y : fv.x);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int e = e0 + u;
             const T phi = (e & 1) ? fv.y : fv.x;
-            const T z = T(e - ph.hz) * T(ph.dz);
+            const int iz = e - ph.hz;
+            const T sz = T(iz);
             cx<T>& q = a[j * U + u];
-            const T n = abs2(q) * sig;
-            const T th = dt * (amp * (vxy + T(ph.cz) * z * z) + gg * n + gdd * phi);
-            if constexpr (RC) {  // real coefficients: imaginary time
+            const T th = kp * phi + (kn * abs2(q) + (cl + kz * sz * sz));
+            if constexpr (kB2) {  // imaginary time, FP32: 2^-th
+                q = __builtin_amdgcn_exp2f(-th) * q;
+            } else if constexpr (RC) {
                 q = (rs * exp_of(-th)) * q;
             } else {
                 T sn, cs;
                 sin_cos(th, &sn, &cs);
-                cs *= rs;
-                sn *= rs;
                 q = cx<T>{q.x * cs + q.y * sn, q.y * cs - q.x * sn};
             }
         }
@@ -1136,6 +1156,12 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
     Phys2 ph{p.dt_nl, p.g, p.gd, amp, p.imag ? 1 : 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
              p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
              0.5 * p.trap[2] * p.trap[2]};
+    // the compiled pass applies sigma only in imaginary time
+    if (sigma && !p.imag) return false;
+    const double b2 = (p.imag && sizeof(T) == 4) ? 1.4426950408889634 : 1.0;  // log2(e)
+    const double ka = b2 * p.dt_nl * amp;
+    const NlConst nl{ka * ph.cx * p.d[0] * p.d[0], ka * ph.cy * p.d[1] * p.d[1],
+                     ka * ph.cz * p.d[2] * p.d[2], b2 * p.dt_nl * p.g, b2 * p.dt_nl * p.gd};
     const cx<double>* tab = (const cx<double>*)p.cntab[2][0];
     const cx<double>* ytab = (const cx<double>*)p.cntab[1][0];
     const int blocks = p.n[0] * (p.n[1] / nb);
@@ -1145,7 +1171,7 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
                        dim3(step2_threads<T, A, B, 16>()), 0, p.stream, (const cx<T>*)psi_in,       \
                        (cx<T>*)psi_out, (T*)phi_out,                                                \
                        (const cx<T>*)p.spec, p.n[0], p.n[1], (const cx<T>*)p.tw[2],                \
-                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph, ytab, kappay, (cx<T>*)ycar, \
+                       (const cx<T>*)p.twr2c, tab, kappa, sigma, ph, nl, ytab, kappay, (cx<T>*)ycar, \
                        phi_sigma ? 1 : 0)
 #define DGPE_CASE(A, B)                                         \
     case A * B:                                                 \
