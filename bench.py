@@ -19,6 +19,10 @@ Default run (one JSON line on stdout):
             stream against its model HBM bytes (and the bytes it moves); HBM
             traffic from the committed rocprofv3 counter summary when it
             matches the sources.
+  hbm_stream_reference  what plain streaming reaches on this part: torch's
+            in-place scale and copy of FP32 arrays of 128 MiB (the 256^3 FP32
+            state, mostly resident in the 256 MB Infinity Cache) and of 1 GiB
+            (beyond it: the HBM rate the 512 x 512 x 256 passes compete with).
   cpu_baseline  the FP64 oracle on the host on a bounded sample (10 steps of
             the same workload from the same state), with the host CPU model.
   precision the FP32 and FP64 GPU states, mu and energy after those steps
@@ -28,6 +32,7 @@ Other modes:
   --profile-run        steps of one workload only (for rocprofv3 runs; --workload,
                        --precision)
   --copy-calibration   a plain device copy of known size (counter calibration)
+  --stream-reference   only the streaming reference (for rocprofv3 runs)
   --summarize DIR      turn rocprofv3 CSV output under DIR into profiles/ text
 """
 import argparse
@@ -209,6 +214,39 @@ def measure(torch, dg, cfg, real_time, dtype, steps, warmup, psi0=None, per_pass
     return out
 
 
+def stream_reference(torch, reps=10):
+    """GB/s (bytes read + written) of torch's in-place scale and of a copy
+    between two arrays, for FP32 arrays of 128 MiB and 1 GiB."""
+    out = {}
+    for mib in (128, 1024):
+        n = (mib << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for kind in ("scale_in_place", "copy"):
+            def go():
+                if kind == "copy":
+                    b.copy_(a)
+                else:
+                    a.mul_(1.0)
+            for _ in range(3):
+                go()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                go()
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / reps
+            gbs = 2.0 * n * 4 / sec / 1e9
+            out[f"{kind}_{mib}MiB_GBs"] = round(gbs, 1)
+            out[f"{kind}_{mib}MiB_frac_of_peak"] = round(gbs / HBM_PEAK_GBS, 4)
+        del a, b
+        torch.cuda.empty_cache()
+    out["kernel"] = "torch elementwise (FP32, in place: mul_(1.0); copy: copy_)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +254,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--profile-run", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--stream-reference", action="store_true")
     ap.add_argument("--summarize", metavar="DIR")
     ap.add_argument("--summary-name", default="")
     ap.add_argument("--traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"))
@@ -266,6 +305,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"copy calibration: 5 copies of {n * 4} bytes")
+        return
+
+    if args.stream_reference:
+        log(f"[bench] streaming reference: {json.dumps(stream_reference(torch))}")
         return
 
     pdtype = torch.complex64 if args.precision == "f32" else torch.complex128
@@ -378,6 +421,10 @@ def main():
         log(f"[bench] 512x512x256 FP32 real time: "
             f"{variants['real_512x512x256_f32']['ms_per_step']:.3f} ms/step")
 
+    stream = stream_reference(torch)
+    log(f"[bench] streaming reference: in place {stream['scale_in_place_128MiB_GBs']} GB/s at 128 MiB, "
+        f"{stream['scale_in_place_1024MiB_GBs']} GB/s at 1 GiB")
+
     cpu = None
     precision = None
     if not args.no_cpu_baseline:
@@ -429,7 +476,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded Gaussian + uniform noise, generated on the host)",
         "config": workload(cfg), "roofline": roofline, "cpu_baseline": cpu, "precision": precision,
-        "variants": variants,
+        "variants": variants, "hbm_stream_reference": stream,
     }
     print(json.dumps(line), flush=True)
 

@@ -743,30 +743,98 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
 namespace dgpe {
 
 
+// Lane shifts inside rows of 16 lanes (DPP row_shr:D, row_shl:D): lane l
+// receives lane l - D (up) or l + D (down) of its row, a lane whose source
+// lies outside its row keeps its own value.  For groups of W <= 16
+// consecutive lanes (W a power of two dividing 16) every source inside the
+// lane's group is inside its row, which is all the wave solver reads.  One
+// VALU move per 32-bit word, instead of an LDS permute.
+template <int CTRL>
+__device__ __forceinline__ int dpp_word(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __int_as_float(dpp_word<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)dpp_word<CTRL>((int)(unsigned)b);
+    const unsigned hi = (unsigned)dpp_word<CTRL>((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int D, typename A>
+__device__ __forceinline__ cx<A> row_up(cx<A> v) {
+    static_assert(D >= 1 && D <= 15, "row shift");
+    return cx<A>{dpp_move<0x110 + D>(v.x), dpp_move<0x110 + D>(v.y)};
+}
+template <int D, typename A>
+__device__ __forceinline__ cx<A> row_down(cx<A> v) {
+    static_assert(D >= 1 && D <= 15, "row shift");
+    return cx<A>{dpp_move<0x100 + D>(v.x), dpp_move<0x100 + D>(v.y)};
+}
+
+// Inclusive scans of the affine maps x -> a x + b over the segments of a line,
+// (a2, b2) o (a1, b1) = (a2 a1, a2 b1 + b2): forward (segment s composes
+// segments 0..s) and backward (segments s..NSEG-1), in log2(NSEG) steps.
+template <int O, int NSEG, bool RC, typename A>
+__device__ __forceinline__ void affine_scan_up(cx<A>& a, cx<A>& b, int seg) {
+    if constexpr (O < NSEG) {
+        const cx<A> ap = row_up<O>(a), bp = row_up<O>(b);
+        if (seg >= O) {
+            b = b + kmul<RC>(a, bp);
+            a = kmul<RC>(a, ap);
+        }
+        affine_scan_up<2 * O, NSEG, RC>(a, b, seg);
+    }
+}
+template <int O, int NSEG, bool RC, typename A>
+__device__ __forceinline__ void affine_scan_down(cx<A>& a, cx<A>& b, int seg) {
+    if constexpr (O < NSEG) {
+        const cx<A> ap = row_down<O>(a), bp = row_down<O>(b);
+        if (seg + O < NSEG) {
+            b = b + kmul<RC>(a, bp);
+            a = kmul<RC>(a, ap);
+        }
+        affine_scan_down<2 * O, NSEG, RC>(a, b, seg);
+    }
+}
+
 // The same exact segmented Crank-Nicolson solve as cn_segment_solve, for
 // lines whose NSEG segments sit on NSEG consecutive lanes of one wave (segment
-// s on lane s of its group; NSEG a power of two dividing 64; full segments).
-// Neighbour values and carries move by wave shuffles, and the carry
+// s on lane s of its group; NSEG a power of two up to 16; full segments).
+// Neighbour values and carries move by DPP row shifts, and the carry
 // recurrences d_end(k) = dtilde_end(k) + Pend(k) d_end(k-1) (and the backward
-// one) are evaluated as an inclusive scan of affine maps x -> a x + b,
-// (a2, b2) o (a1, b1) = (a2 a1, a2 b1 + b2), in log2(NSEG) steps.  No LDS and
-// no barriers.  Tables: alpha, P, Q (length N) and pend, qbeg (per segment).
+// one) are evaluated as inclusive scans of affine maps in log2(NSEG) steps.
+// No LDS and no barriers.  Tables: alpha, P, and Q or G (length N; ta, tp, tq
+// point at this segment's S entries), pend, qbeg and H (per segment).
+// Values stored narrower than the arithmetic (FP32 state, FP64 real-time
+// recurrences) are rounded once: the back substitution runs once, from the
+// true x after the segment, and the segment's first x from a zero right
+// carry, which the backward scan needs, is accumulated in the forward pass,
+// x_first = sum_i G_i d_i = sum_i G_i dloc_i + H c_left (tq then holds G).
 template <typename T, int S, int NSEG, bool RC, typename TT, typename TS, typename VS>
 __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
                                                       cx<cn_acc_t<T, RC>> kappa, const TT* ta,
                                                       const TT* tp, const TT* tq, const TS* pend,
-                                                      const TS* qbeg, int seg) {
-    // ta, tp, tq point at this segment's S entries
+                                                      const TS* qbeg, int seg,
+                                                      const TS* hs = nullptr) {
+    static_assert(NSEG >= 1 && NSEG <= 16 && (NSEG & (NSEG - 1)) == 0, "segments inside a row");
     using A = cn_acc_t<T, RC>;
+    constexpr bool kNarrow = sizeof(VS) < sizeof(A);
     const cx<A> zero = {A(0), A(0)};
     // neighbours
-    cx<A> left = widen<A>(shfl_up_c(v[S - 1], 1, NSEG));
-    cx<A> right = widen<A>(shfl_down_c(v[0], 1, NSEG));
-    if (seg == 0) left = zero;
-    if (seg == NSEG - 1) right = zero;
+    cx<A> left = zero, right = zero;
+    if constexpr (NSEG > 1) {
+        left = widen<A>(row_up<1>(v[S - 1]));
+        right = widen<A>(row_down<1>(v[0]));
+        if (seg == 0) left = zero;
+        if (seg == NSEG - 1) right = zero;
+    }
     // forward recurrence from a zero carry, r'_i = u_{i-1} + u_{i+1} + kappa u_i
     // formed on the fly from the input values
-    cx<A> dcur = zero;
+    cx<A> dcur = zero, xacc = zero;
     {
         cx<A> prev = left, cur = widen<A>(v[0]);
 #pragma unroll
@@ -774,57 +842,65 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
             const cx<A> nxt = (i + 1 < S) ? widen<A>(v[(i + 1 < S) ? i + 1 : i]) : right;
             dcur = kmul<RC>(widen<A>(ta[i]), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
             v[i] = to_store<VS>(dcur);
+            // narrow storage: rounded here, so that the wide value dies (the
+            // scheduler otherwise keeps all S wide values live through the scan)
+            if constexpr (kNarrow) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
             prev = cur;
             cur = nxt;
         }
     }
-    // inclusive scan over the segments of the line: d_end(s)
+    // forward scan: d at the end of each segment; its left neighbour's is the
+    // true d before the segment
     cx<A> a = widen<A>(pend[seg]), b = dcur;
-#pragma unroll
-    for (int o = 1; o < NSEG; o <<= 1) {
-        const cx<A> ap = shfl_up_c(a, o, NSEG), bp = shfl_up_c(b, o, NSEG);
-        if (seg >= o) {
-            b = b + kmul<RC>(a, bp);
-            a = kmul<RC>(a, ap);
-        }
+    affine_scan_up<1, NSEG, RC>(a, b, seg);
+    cx<A> c = zero;
+    if constexpr (NSEG > 1) {
+        c = row_up<1>(b);
+        if (seg == 0) c = zero;
     }
-    cx<A> c = shfl_up_c(b, 1, NSEG);
-    if (seg == 0) c = zero;
-    // P correction and back substitution from a zero carry.  FP64 factors are
-    // read again here rather than kept live since the forward pass (64 registers)
+    // FP64 factors are read again below rather than kept live since the
+    // forward pass (64 registers)
     if constexpr (sizeof(A) == 8) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // (narrower storage than arithmetic: the back substitution runs twice, the
-    // second time from the true right carry, so that each x is rounded once;
-    // see cn_segment_solve)
-    constexpr bool kTwice = sizeof(VS) < sizeof(A);
+    // the segment's first x from a zero right carry
     cx<A> xcur = zero;
+    if constexpr (kNarrow) {
+        // the G entries are read after the scan (a zero offset that depends on
+        // its result keeps the scheduler from hoisting the reads and holding
+        // them through it)
+        int o = 0;
+        asm volatile("" : "+v"(o) : "v"(c.x));
 #pragma unroll
-    for (int i = S - 1; i >= 0; --i) {
-        const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c);
-        xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
-        if constexpr (!kTwice) v[i] = to_store<VS>(xcur);
-    }
-    // scan from the right: true x at the start of each segment
-    a = widen<A>(qbeg[seg]);
-    b = xcur;
-#pragma unroll
-    for (int o = 1; o < NSEG; o <<= 1) {
-        const cx<A> ap = shfl_down_c(a, o, NSEG), bp = shfl_down_c(b, o, NSEG);
-        if (seg + o < NSEG) {
-            b = b + kmul<RC>(a, bp);
-            a = kmul<RC>(a, ap);
-        }
-    }
-    cx<A> cr = shfl_down_c(b, 1, NSEG);
-    if (seg == NSEG - 1) cr = zero;
-    if constexpr (kTwice) {
-        // the factors are read again (not kept live through the scan)
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        xcur = cr;
+        for (int i = 0; i < S; ++i) xacc = xacc + kmul<RC>(widen<A>(tq[o + i]), widen<A>(v[i]));
+        xcur = xacc + kmul<RC>(widen<A>(hs[seg]), c);
+    } else {
+        // P correction and back substitution from a zero carry
 #pragma unroll
         for (int i = S - 1; i >= 0; --i) {
             const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c);
             xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
+            v[i] = to_store<VS>(xcur);
+        }
+    }
+    // backward scan: true x at the start of each segment; the right
+    // neighbour's is the true x after the segment
+    a = widen<A>(qbeg[seg]);
+    b = xcur;
+    affine_scan_down<1, NSEG, RC>(a, b, seg);
+    cx<A> cr = zero;
+    if constexpr (NSEG > 1) {
+        cr = row_down<1>(b);
+        if (seg == NSEG - 1) cr = zero;
+    }
+    if constexpr (kNarrow) {
+        // P correction and the one back substitution, from the true x after
+        // the segment (the factors read here, not held through the scans)
+        int o = 0;
+        asm volatile("" : "+v"(o) : "v"(cr.x));
+        xcur = cr;
+#pragma unroll
+        for (int i = S - 1; i >= 0; --i) {
+            const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[o + i]), c);
+            xcur = d + kmul<RC>(widen<A>(ta[o + i]), xcur);
             v[i] = to_store<VS>(xcur);
         }
     } else {
