@@ -72,9 +72,11 @@ __device__ __forceinline__ void quadrant(int q, T sr, T cr, T* s, T* c) {
 }
 }  // namespace detail
 
-__device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
+// The reduced argument's sin r and cos r - 1 (the cosine series without its
+// leading 1), and the quadrant q
+__device__ __forceinline__ void sin_cosm1_reduced(float x, int* q, float* sr, float* cm1r) {
     const float k = rintf(x * 0.636619772f);
-    const int q = int(k) & 3;
+    *q = int(k) & 3;
     const float r = fmaf(-k, -4.37113883e-08f, fmaf(-k, 1.57079637f, x));
     const float r2 = r * r;
     // sin r = r (1 - r^2/3! + r^4/5! - r^6/7! + r^8/9!)
@@ -82,20 +84,18 @@ __device__ __forceinline__ void sin_cos(float x, float* s, float* c) {
     ps = fmaf(ps, r2, -1.0f / 5040.0f);
     ps = fmaf(ps, r2, 1.0f / 120.0f);
     ps = fmaf(ps, r2, -1.0f / 6.0f);
-    const float sr = fmaf(r * r2, ps, r);
-    // cos r = 1 - r^2/2! + r^4/4! - ... - r^10/10!
+    *sr = fmaf(r * r2, ps, r);
+    // cos r - 1 = -r^2/2! + r^4/4! - ... - r^10/10!
     float pc = -1.0f / 3628800.0f;
     pc = fmaf(pc, r2, 1.0f / 40320.0f);
     pc = fmaf(pc, r2, -1.0f / 720.0f);
     pc = fmaf(pc, r2, 1.0f / 24.0f);
     pc = fmaf(pc, r2, -0.5f);
-    const float cr = fmaf(r2, pc, 1.0f);
-    detail::quadrant(q, sr, cr, s, c);
+    *cm1r = r2 * pc;
 }
 
-__device__ __forceinline__ void sin_cos(double x, double* s, double* c) {
-    int q;
-    const double r = detail::reduce_pio2(x, &q);
+__device__ __forceinline__ void sin_cosm1_reduced(double x, int* q, double* sr, double* cm1r) {
+    const double r = detail::reduce_pio2(x, q);
     const double r2 = r * r;
     // odd Taylor terms through r^17, even ones through r^18: coefficients
     // (-1)^n / (2n+1)! and (-1)^n / (2n)!
@@ -108,13 +108,40 @@ __device__ __forceinline__ void sin_cos(double x, double* s, double* c) {
     double ps = S[8];
 #pragma unroll
     for (int i = 7; i >= 1; --i) ps = fma(ps, r2, S[i]);
-    const double sr = fma(r * r2, ps, r);
+    *sr = fma(r * r2, ps, r);
     double pc = C[9];
 #pragma unroll
     for (int i = 8; i >= 1; --i) pc = fma(pc, r2, C[i]);
-    const double cr = fma(r2, pc, 1.0);
-    detail::quadrant(q, sr, cr, s, c);
+    *cm1r = r2 * pc;
 }
+
+template <typename T>
+__device__ __forceinline__ void sin_cos(T x, T* s, T* c) {
+    int q;
+    T sr, cm1r;
+    sin_cosm1_reduced(x, &q, &sr, &cm1r);
+    detail::quadrant(q, sr, T(1) + cm1r, s, c);
+}
+
+// psi e^{-i theta}, formed as psi + psi (e^{-i theta} - 1) with cos theta - 1
+// taken from its series without the leading 1 in the first quadrant (in the
+// others |cos theta - 1| >= 1 - 1/sqrt 2 and c - 1 loses nothing).  cos theta
+// itself, rounded to the state's precision near theta = 0, is off by up to half
+// an ulp of 1 with one sign over neighbouring points and steps: |e^{-i theta}|
+// then differs from 1 by about that much and the real-time norm drifts.  The
+// increment psi (e^{-i theta} - 1) keeps its full relative precision, so the
+// modulus error is of order theta^2 eps, and the result is rounded once.
+template <typename T>
+__device__ __forceinline__ cx<T> rotate_phase(cx<T> q, T th) {
+    int qd;
+    T sr, cm1r;
+    sin_cosm1_reduced(th, &qd, &sr, &cm1r);
+    T s, c;
+    detail::quadrant(qd, sr, T(1) + cm1r, &s, &c);
+    const T cm1 = qd == 0 ? cm1r : c - T(1);
+    return cx<T>{q.x + fma(q.y, s, q.x * cm1), q.y + fma(-q.x, s, q.y * cm1)};
+}
+
 // exp(x) = 2^(x log2 e) on the hardware base-2 exponential (v_exp_f32, about
 // 1 ulp): the product's rounding adds |x| eps relative, negligible for the
 // imaginary-time factors exp(-theta), theta = dt (...) << 1, and it takes 2

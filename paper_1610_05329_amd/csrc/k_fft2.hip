@@ -853,9 +853,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
             } else if constexpr (RC) {
                 q = (rs * exp_of(-th)) * q;
             } else {
-                T sn, cs;
-                sin_cos(th, &sn, &cs);
-                q = cx<T>{q.x * cs + q.y * sn, q.y * cs - q.x * sn};
+                q = rotate_phase(q, th);
             }
         }
     }

@@ -235,9 +235,7 @@ __global__ void __launch_bounds__(kRedThreads)
             w = cx<T>{u.x * e, u.y * e};
             acc += double(w.x) * w.x + double(w.y) * w.y;
         } else {
-            T sn, cs;
-            sin_cos(th, &sn, &cs);
-            w = cx<T>{u.x * cs + u.y * sn, u.y * cs - u.x * sn};
+            w = rotate_phase(u, th);
         }
         psi[i] = w;
     }

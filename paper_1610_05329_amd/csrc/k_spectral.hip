@@ -400,11 +400,7 @@ __global__ void __launch_bounds__(256) k_c2r_step(const cx<T>* psi_in, cx<T>* ps
                     const T f = rs * exp_of(-th);
                     r = f * a[u];
                 } else {
-                    T sn, cs;
-                    sin_cos(th, &sn, &cs);
-                    cs *= rs;
-                    sn *= rs;
-                    r = cx<T>{a[u].x * cs + a[u].y * sn, a[u].y * cs - a[u].x * sn};
+                    r = rs * rotate_phase(a[u], th);
                 }
                 P[e * ES + b] = r;
             }
