@@ -12,7 +12,12 @@ Default run (one JSON line on stdout):
   variants  the same workload in FP64; the same grid and parameters in real time
             (FP32 and FP64); the FP32 real-time adjoint (forward, recompute
             and reverse sweeps, per forward step); the 512 x 512 x 256 FP32
-            real-time workload.  Each with its fraction of the HBM peak on the
+            real-time workload.  The paths beyond the plain step: the
+            symmetric (Strang) step at 256^3 (FP32, both time modes), the
+            ground-state driver on the 128^3 preparation (FP64, to a mu change
+            below 1e-10 per step), quasi-2D plans at 1024 x 1024 (FP32, both
+            time modes), the overlap-objective adjoint at 256^3 (FP32) and the
+            binary density file of the 256^3 state.  Each with its fraction of the HBM peak on the
             bytes its passes move and on the model bytes (22 s per point per
             step, s = bytes per real; 82 s for the adjoint).
   roofline  per-pass HIP event timing of the dominant pass on the plan's
@@ -183,19 +188,25 @@ def frac(bytes_, seconds):
     return round(bytes_ / seconds / 1e9 / HBM_PEAK_GBS, 4)
 
 
-def measure(torch, dg, cfg, real_time, dtype, steps, warmup, psi0=None, per_pass=True):
+def measure(torch, dg, cfg, real_time, dtype, steps, warmup, psi0=None, per_pass=True, scheme=None,
+            q2d=None):
     """Time `steps` plain steps of one workload; the step's rate, bytes moved
     (the passes' own counts) and model bytes against the HBM peak, and the
     per-pass event timing."""
     import workloads as W
     s = 4 if dtype == torch.complex64 else 8
-    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=real_time, dtype=dtype)
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=real_time, dtype=dtype,
+                   q2d=q2d)
+    if scheme:
+        plan.set("scheme", scheme)
     init = plan.new_state(W.noisy_gaussian(cfg) if psi0 is None else psi0)
     psi = init.clone()
     wall, _ = timed_steps(torch, plan, psi, init, steps, warmup)
     assert torch.isfinite(torch.view_as_real(psi)).all().item(), "non-finite state"
     moved = sum(plan.pass_bytes().values())
-    model = MODEL_S_PER_POINT * s * cfg.npoints
+    # model bytes of the plain step (3D: 22 s per point; quasi-2D has no y
+    # transforms and no y sweep: 14 s)
+    model = (MODEL_S_PER_POINT - (8 if q2d else 0)) * s * cfg.npoints
     out = {"value": cfg.npoints * steps / wall, "ms_per_step": wall * 1e3 / steps, "steps": steps,
            "grid": list(cfg.n), "time": "real" if real_time else "imaginary",
            "dtype": "f32" if s == 4 else "f64", "fused_y": plan.fused_y,
@@ -210,6 +221,83 @@ def measure(torch, dg, cfg, real_time, dtype, steps, warmup, psi0=None, per_pass
                                 for k, v in ms.items() if v > 0 and pb[k] > 1e6}
     plan.close()
     del plan, psi, init
+    torch.cuda.empty_cache()
+    return out
+
+
+def widened(torch, dg, np, W, cfg, psi0):
+    """Measurements of the paths beyond the plain step (see the module doc)."""
+    out = {}
+    lie = {}
+    for real_time in (False, True):
+        mode = "real" if real_time else "imag"
+        k = f"strang_256cubed_f32_{mode}"
+        out[k] = measure(torch, dg, cfg, real_time, torch.complex64, 20, 5, psi0, per_pass=False,
+                         scheme="strang")
+        lie[mode] = measure(torch, dg, cfg, real_time, torch.complex64, 20, 5, psi0,
+                            per_pass=False)["ms_per_step"]
+        out[k]["ms_per_step_first_order_step"] = lie[mode]
+        out[k].pop("step_bytes_moved")  # the passes' counts are those of the first-order step
+        out[k].pop("step_frac_of_peak")
+        out[k].pop("step_model_bytes")
+        out[k].pop("step_frac_of_peak_model_bytes")
+        log(f"[bench] symmetric step 256^3 FP32 {mode}: {out[k]['ms_per_step']:.3f} ms/step "
+            f"(first-order {lie[mode]:.3f})")
+    # the ground-state driver on the 128^3 preparation (gd = 15, FP64)
+    q = W.CONFIGS["quench_128cubed"]
+    plan = dg.Plan(q.n, q.d, q.dt, q.trap, q.g, 15.0, real_time=False, dtype=torch.complex128)
+    psi = plan.new_state(W.gaussian_state(q.n, q.d, q.trap))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.ground_state(psi, tol=1e-10, max_steps=20000, check_every=10)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    out["ground_state_128cubed_f64"] = {
+        "steps": res["steps"], "converged": bool(res["converged"]), "seconds": sec,
+        "ms_per_step": sec * 1e3 / max(res["steps"], 1), "dmu_per_step": res["dmu_per_step"],
+        "mu": res["observables"]["mu"], "tol": 1e-10, "check_every": 10}
+    log(f"[bench] ground state 128^3 FP64: {res['steps']} steps in {sec:.2f} s")
+    plan.close()
+    del plan, psi
+    # quasi-2D (dipoles along the tight axis) at 1024 x 1024
+    c2 = W.Config("q2d_1024x1024", (1024, 1, 1024), (0.05, 1.0, 0.05), 0.0005, (1.0, 10.0, 1.0),
+                  100.0, 60.0, True, 100, noise=1e-3, seed=6)
+    for real_time in (False, True):
+        mode = "real" if real_time else "imag"
+        k = f"q2d_1024x1024_f32_{mode}"
+        out[k] = measure(torch, dg, c2, real_time, torch.complex64, 100, 10, per_pass=False, q2d="perp")
+        log(f"[bench] quasi-2D 1024x1024 FP32 {mode}: {out[k]['ms_per_step']:.3f} ms/step")
+    # overlap-objective adjoint at 256^3 (FP32, real time, 40 steps, checkpoints every 10)
+    na = 40
+    plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=torch.complex64)
+    psia = plan.new_state(psi0)
+    tgt = plan.new_state(W.gaussian_state(cfg.n, cfg.d, cfg.trap))
+    amp = np.ones(na + 1)
+    plan.adjoint(psia, amp[:3], ckpt_every=2, objective="overlap", target=tgt)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = plan.adjoint(psia, amp, ckpt_every=10, objective="overlap", target=tgt)
+    torch.cuda.synchronize()
+    wa = time.perf_counter() - t0
+    out["adjoint_overlap_f32"] = {"value": cfg.npoints * na / wa, "ms_per_step": wa * 1e3 / na,
+                                  "steps": na, "ckpt_every": 10, "objective": "overlap", "J": res["J"]}
+    log(f"[bench] overlap adjoint FP32: {wa * 1e3 / na:.3f} ms per forward step")
+    del res
+    # the binary density file (FP64 [x][y][z]) of the 256^3 state
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "density.bin")
+        plan.write_density(psia, path)  # warm-up
+        t0 = time.perf_counter()
+        plan.write_density(psia, path)
+        sec = time.perf_counter() - t0
+        nbytes = os.path.getsize(path)
+    out["density_file_256cubed"] = {"bytes": nbytes, "seconds": sec, "GBs": nbytes / sec / 1e9,
+                                    "note": "device density kernel, device-to-host copy and file "
+                                            "write (page cache)"}
+    log(f"[bench] density file 256^3: {nbytes / 1e6:.0f} MB in {sec * 1e3:.1f} ms")
+    plan.close()
+    del plan, psia, tgt
     torch.cuda.empty_cache()
     return out
 
@@ -420,6 +508,7 @@ def main():
         variants["real_512x512x256_f32"] = measure(torch, dg, big, True, torch.complex64, 20, 5)
         log(f"[bench] 512x512x256 FP32 real time: "
             f"{variants['real_512x512x256_f32']['ms_per_step']:.3f} ms/step")
+        variants.update(widened(torch, dg, np, W, cfg, psi0))
 
     stream = stream_reference(torch)
     log(f"[bench] streaming reference: in place {stream['scale_in_place_128MiB_GBs']} GB/s at 128 MiB, "
