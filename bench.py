@@ -15,7 +15,7 @@ Default run (one JSON line on stdout):
             real-time workload.  The paths beyond the plain step: the
             symmetric (Strang) step at 256^3 (FP32, both time modes), the
             ground-state driver on the 128^3 preparation (FP64, to a mu change
-            below 1e-10 per step), quasi-2D plans at 1024 x 1024 (FP32, both
+            below 1e-10 per step), quasi-2D plans at 2048 x 2048 (FP32, both
             time modes), the overlap-objective adjoint at 256^3 (FP32) and the
             binary density file of the 256^3 state.  Each with its fraction of the HBM peak on the
             bytes its passes move and on the model bytes (22 s per point per
@@ -259,14 +259,14 @@ def widened(torch, dg, np, W, cfg, psi0):
     log(f"[bench] ground state 128^3 FP64: {res['steps']} steps in {sec:.2f} s")
     plan.close()
     del plan, psi
-    # quasi-2D (dipoles along the tight axis) at 1024 x 1024
-    c2 = W.Config("q2d_1024x1024", (1024, 1, 1024), (0.05, 1.0, 0.05), 0.0005, (1.0, 10.0, 1.0),
+    # quasi-2D (dipoles along the tight axis) at 2048 x 2048, the largest plane
+    c2 = W.Config("q2d_2048x2048", (2048, 1, 2048), (0.025, 1.0, 0.025), 0.0002, (1.0, 10.0, 1.0),
                   100.0, 60.0, True, 100, noise=1e-3, seed=6)
     for real_time in (False, True):
         mode = "real" if real_time else "imag"
-        k = f"q2d_1024x1024_f32_{mode}"
+        k = f"q2d_2048x2048_f32_{mode}"
         out[k] = measure(torch, dg, c2, real_time, torch.complex64, 100, 10, per_pass=False, q2d="perp")
-        log(f"[bench] quasi-2D 1024x1024 FP32 {mode}: {out[k]['ms_per_step']:.3f} ms/step")
+        log(f"[bench] quasi-2D 2048x2048 FP32 {mode}: {out[k]['ms_per_step']:.3f} ms/step")
     # overlap-objective adjoint at 256^3 (FP32, real time, 40 steps, checkpoints every 10)
     na = 40
     plan = dg.Plan(cfg.n, cfg.d, cfg.dt, cfg.trap, cfg.g, cfg.gd, real_time=True, dtype=torch.complex64)

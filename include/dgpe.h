@@ -40,7 +40,8 @@
  * Errors: every call returns a dgpe_status; dgpe_last_error() gives a
  * thread-local message for the last failure.  Grid sizes must be even, have no
  * prime factor other than 2 and 3 (the paper's FFT-friendly sizes restricted to
- * the radices implemented here) and lie in [4, 1024]; invalid arguments are
+ * the radices implemented here) and lie in [4, 2048], with at most 2^30 points
+ * in all (the kernels index points with 32-bit integers); invalid arguments are
  * rejected before any work is enqueued (the library's counterpart of the
  * paper's input checks, "Additional comments").
  */
@@ -129,7 +130,8 @@ typedef struct {
 size_t dgpe_workspace_bytes(const int32_t n[3], uint32_t mode);
 
 /* Create a plan.
- *   n[3]        Nx, Ny, Nz (each even, 2^a 3^b, 4..1024; Ny = 1 for quasi-2D)
+ *   n[3]        Nx, Ny, Nz (each even, 2^a 3^b, 4..2048, at most 2^30 points;
+ *               Ny = 1 for quasi-2D)
  *   d[3]        grid spacings > 0
  *   dt          time step > 0
  *   trap[3]     nu, lambda, gamma (trap frequencies along x, y, z), finite

@@ -46,7 +46,11 @@ dgpe_status fail(dgpe_status s, const std::string& msg) {
 constexpr size_t kAlign = 256;
 constexpr int kThreads = 256;
 constexpr int kEmax = 16;
+// LDS per block: the block shapes are chosen within 64 KB where they can be
+// (several blocks per CU); a pass whose one-line block needs more takes up to
+// the 160 KB a gfx950 workgroup may hold (one block per CU)
 constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kLdsMax = 160 * 1024;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -55,13 +59,20 @@ bool q2d_mode(uint32_t mode) { return (mode & (DGPE_Q2D_PERP | DGPE_Q2D_INPLANE)
 
 bool size_ok(int n);
 
+// at most 2^30 points (the kernels index points and lines with 32-bit integers)
+constexpr int kMaxAxis = 2048;
+constexpr int64_t kMaxPoints = int64_t(1) << 30;
+
+bool points_ok(const int32_t n[3]) { return (int64_t)n[0] * n[1] * n[2] <= kMaxPoints; }
+
 bool grid_ok(const int32_t n[3], uint32_t mode) {
+    if (!points_ok(n)) return false;
     if (q2d_mode(mode)) return n[1] == 1 && size_ok(n[0]) && size_ok(n[2]);
     return size_ok(n[0]) && size_ok(n[1]) && size_ok(n[2]);
 }
 
 bool size_ok(int n) {
-    if (n < 4 || n > 1024 || (n & 1)) return false;
+    if (n < 4 || n > kMaxAxis || (n & 1)) return false;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
     return n == 1;
@@ -104,7 +115,7 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
     // z passes: B lines, B | Ny, B*M <= cap, LDS within budget
     int Bz = f32 ? 16 : 8;
     while (Bz > 1 && (Ny % Bz || Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsBudget)) Bz >>= 1;
-    if (Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsBudget) return false;
+    if (Bz * M > cap || c2r_step_lds(Nz, Bz, csz) > kLdsMax) return false;
     lc->logB_z = ilog2(Bz);
     // z segments (16 or 32 points): B * nseg <= threads
     int sz = 16;
@@ -114,13 +125,13 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
     // y rows
     int By = f32 ? 16 : 8;
     while (By > 1 && (By * Ny > cap || (size_t)(Ny * (By + 1) + Ny) * csz > kLdsBudget)) By >>= 1;
-    if ((size_t)(Ny * (By + 1) + Ny) * csz > kLdsBudget || By * Ny > cap) return false;
+    if ((size_t)(Ny * (By + 1) + Ny) * csz > kLdsMax || By * Ny > cap) return false;
     lc->logB_y = ilog2(By);
     // x columns: B | Ny
     int Bx = f32 ? 16 : 8;
     while (Bx > 1 && (Ny % Bx || Bx * Nx > cap || (size_t)(Nx * (Bx + 1) + Nx) * csz > kLdsBudget))
         Bx >>= 1;
-    if (Bx * Nx > cap || (size_t)(Nx * (Bx + 1) + Nx) * csz > kLdsBudget) return false;
+    if (Bx * Nx > cap || (size_t)(Nx * (Bx + 1) + Nx) * csz > kLdsMax) return false;
     lc->logB_x = ilog2(Bx);
     // strided sweeps: columns C, segments S, ZB | C; FP32 blocks up to 1024
     // threads, FP64 up to 512 (register budget of the segment arrays)
@@ -145,7 +156,7 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
         int zb = narrow ? 32 : 16;
         auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * nseg * (S + 1) + 3 * nseg) * asz; };
         while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
-        if (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget) return false;
+        if (C % zb || nseg * zb > tmax || lds(zb) > kLdsMax) return false;
         lc->seg[axis] = S;
         lc->logZB[axis] = ilog2(zb);
     }
@@ -685,7 +696,8 @@ dgpe_status check_plan_args(const int32_t n[3], const double d[3], double dt, co
         if (!(q2d_mode(mode) && a == 1) && !size_ok(n[a]))
             return fail(DGPE_EUNSUPPORTED_SIZE,
                         "grid size " + std::to_string(n[a]) +
-                            " must be even, of the form 2^a 3^b, and in [4, 1024]");
+                            " must be even, of the form 2^a 3^b, and in [4, 2048]");
+    if (!points_ok(n)) return fail(DGPE_EUNSUPPORTED_SIZE, "the grid has more than 2^30 points");
     for (int a = 0; a < 3; ++a)
         if (!(d[a] > 0) || !std::isfinite(d[a])) return fail(DGPE_EINVAL, "spacings must be finite and > 0");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(DGPE_EINVAL, "dt must be finite and > 0");

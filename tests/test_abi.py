@@ -43,7 +43,8 @@ def test_workspace_bytes_accepts_fft_friendly_sizes(lib):
             assert lib.dgpe_workspace_bytes(_n(*n), mode) > 0, (n, mode)
 
 
-@pytest.mark.parametrize("bad", [(10, 32, 32), (32, 5, 32), (32, 32, 7), (2048, 32, 32), (2, 8, 8), (40, 40, 40)])
+@pytest.mark.parametrize("bad", [(10, 32, 32), (32, 5, 32), (32, 32, 7), (4096, 32, 32), (2, 8, 8), (40, 40, 40),
+                                 (2048, 2048, 512)])  # the last: more than 2^30 points
 def test_workspace_bytes_rejects_other_sizes(lib, bad):
     assert lib.dgpe_workspace_bytes(_n(*bad), 0) == 0
 
