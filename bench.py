@@ -225,6 +225,15 @@ def measure(torch, dg, cfg, real_time, dtype, steps, warmup, psi0=None, per_pass
     return out
 
 
+def _q2d_config():
+    import workloads as W
+    return W.Config("q2d_2048x2048", (2048, 1, 2048), (0.025, 1.0, 0.025), 0.0002, (1.0, 10.0, 1.0),
+                    100.0, 60.0, True, 100, noise=1e-3, seed=6)
+
+
+Q2D_2048 = _q2d_config()
+
+
 def widened(torch, dg, np, W, cfg, psi0):
     """Measurements of the paths beyond the plain step (see the module doc)."""
     out = {}
@@ -260,8 +269,7 @@ def widened(torch, dg, np, W, cfg, psi0):
     plan.close()
     del plan, psi
     # quasi-2D (dipoles along the tight axis) at 2048 x 2048, the largest plane
-    c2 = W.Config("q2d_2048x2048", (2048, 1, 2048), (0.025, 1.0, 0.025), 0.0002, (1.0, 10.0, 1.0),
-                  100.0, 60.0, True, 100, noise=1e-3, seed=6)
+    c2 = Q2D_2048
     for real_time in (False, True):
         mode = "real" if real_time else "imag"
         k = f"q2d_2048x2048_f32_{mode}"
@@ -355,7 +363,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=40)
     ap.add_argument("--workload", choices=["imag_256cubed", "real_256cubed", "real_512x512x256",
-                                           "adjoint_256cubed"],
+                                           "adjoint_256cubed", "q2d_2048", "q2d_2048_real"],
                     default="imag_256cubed",
                     help="workload of --profile-run (the JSON line always uses imag_256cubed); "
                          "real_256cubed = the same grid and parameters in real time; "
@@ -409,6 +417,19 @@ def main():
         plan_a.adjoint(psia, amp, ckpt_every=10)
         torch.cuda.synchronize()
         log("[bench] adjoint profile run done")
+        return
+    if args.profile_run and args.workload.startswith("q2d_2048"):
+        c2 = Q2D_2048
+        log(f"[bench] profile run {args.workload} {args.precision}")
+        plan = dg.Plan(c2.n, c2.d, c2.dt, c2.trap, c2.g, c2.gd, real_time=args.workload.endswith("real"),
+                       dtype=pdtype, q2d="perp")
+        psi_init = plan.new_state(W.noisy_gaussian(c2))
+        psi = psi_init.clone()
+        for k in (args.warmup, args.steps):
+            psi.copy_(psi_init)
+            plan.step(psi, min(k, CHUNK))
+        torch.cuda.synchronize()
+        log("[bench] profile run done")
         return
     if args.profile_run:
         name = "imag_256cubed" if args.workload == "real_256cubed" else args.workload
