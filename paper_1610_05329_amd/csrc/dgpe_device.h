@@ -610,10 +610,11 @@ __device__ __forceinline__ void tab_stage(const TabRegs<V, N, NT>& r, D* dst, in
     for (int u = 0; u < TabRegs<V, N, NT>::R; ++u) dst[index(min(tid + u * NT, N - 1))] = widen<typename D::value_type>(r.v[u]);
 }
 
-// conversion between the arithmetic type and the segment values' type.  The
-// segment values stay in the arithmetic type: rounding the real-time FP64
-// intermediates (r', d) to FP32 between the passes was measured to lose norm
-// steadily (1e-8 per step at 128^3), unlike one rounding of the result
+// conversion between the arithmetic type and the segment values' type.  Values
+// held narrower than the arithmetic (FP32 segments of the FP64 real-time
+// recurrences) are rounded once each: the forward d, and each x from the true
+// right carry (rounding r', or an x before its carry correction, was measured
+// to drift the real-time norm by about 1e-8 per step at 128^3)
 template <typename V, typename A>
 __device__ __forceinline__ cx<V> to_store(cx<A> v) { return cx<V>{V(v.x), V(v.y)}; }
 
