@@ -521,6 +521,18 @@ def main():
                                    "J": out["J"], "step_model_bytes": amodel,
                                    "step_frac_of_peak_model_bytes": frac(amodel * na, wa)}
         log(f"[bench] adjoint FP32: {wa * 1e3 / na:.3f} ms per forward step")
+        # every state and its Phi kept (ckpt_every = 1): no recompute
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out1 = plan_a.adjoint(psia, amp, ckpt_every=1)
+        torch.cuda.synchronize()
+        w1 = time.perf_counter() - t0
+        variants["adjoint_f32_keep_all"] = {
+            "value": cfg.npoints * na / w1, "ms_per_step": w1 * 1e3 / na, "steps": na, "ckpt_every": 1,
+            "objective": "energy", "J": out1["J"], "same_J_as_ckpt_10": out1["J"] == out["J"],
+            "adjoint_workspace_GiB": plan_a.lib.dgpe_adjoint_workspace_bytes(plan_a.handle, na, 1) / 2**30}
+        log(f"[bench] adjoint FP32, every state kept: {w1 * 1e3 / na:.3f} ms per forward step")
+        del out1
         plan_a.close()
         del plan_a, psia, out
         torch.cuda.empty_cache()

@@ -249,7 +249,12 @@ size_t dgpe_adjoint_workspace_bytes(dgpe_plan plan, int32_t nsteps, int32_t ckpt
  *             device state of the plan precision).
  *   adj_ws    device buffer of >= dgpe_adjoint_workspace_bytes(); holds the
  *             checkpoints (every ckpt_every steps), one segment of recomputed
- *             states and the dipolar potential of each of them.
+ *             states and the dipolar potential of each of them.  ckpt_every = 1
+ *             keeps every state psi_1..psi_N and the potential of every state
+ *             psi_0..psi_{N-1} from the forward sweep, so that nothing is
+ *             recomputed (nsteps states and nsteps real arrays: at 256^3 FP32
+ *             192 MiB per step, for a memory of 288 GB).  The result does not
+ *             depend on ckpt_every (bitwise).
  * Outputs (host unless stated): J; dJ_damp[nsteps+1]; dJ_dtrap[3] for
  * (nu, lambda, gamma); psi_final (device, nullable) = psi_N; dJ_dpsi0 (device,
  * nullable) = the cotangent lam_0 with dJ = Re sum conj(lam_0) dpsi0.

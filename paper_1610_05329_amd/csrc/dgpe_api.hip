@@ -543,27 +543,32 @@ struct AdjLayout {
     int nckpt;
 };
 
+// K > 1: a checkpoint every K steps and one segment of K recomputed states
+// with their Phi.  K = 1: every state psi_1..psi_N and the Phi of every state
+// psi_0..psi_{N-1}, kept from the forward sweep (no recompute).
 AdjLayout adj_layout(const Plan& p, int nsteps, int K) {
     AdjLayout L{};
     const size_t nt = (size_t)p.n[0] * p.n[1] * p.n[2];
     const size_t csz = p.f32 ? 8 : 16, rsz = p.f32 ? 4 : 8;
     const size_t st = align_up(nt * csz);
+    const bool all = K == 1;
+    const int nphi = all ? nsteps : K;  // Phi slots and partial sets
     L.nckpt = (nsteps + K - 1) / K;
     size_t o = 0;
     L.ckpt = o;
     o += st * (size_t)std::max(L.nckpt, 1);
     L.seg = o;
-    o += st * (size_t)K;
+    o += st * (size_t)(all ? 0 : K);
     L.lam = o;
     o += st;
-    L.phin = o;  // Phi of the segment's states, one slot per step
-    o += align_up(nt * rsz) * (size_t)K;
+    L.phin = o;  // Phi of the states, one slot per step
+    o += align_up(nt * rsz) * (size_t)nphi;
     L.phis = o;
     o += align_up(nt * rsz);
     L.sums = o;
     o += align_up((size_t)(nsteps + 1) * 4 * sizeof(double));
-    L.part = o;  // partials: one set per step of a segment
-    o += align_up(red_count_for(p.n, p.lc) * sizeof(double)) * (size_t)K;
+    L.part = o;  // partials: one set per step of a segment (of the run for K = 1)
+    o += align_up(red_count_for(p.n, p.lc) * sizeof(double)) * (size_t)nphi;
     L.scratch = o;
     o += align_up(16 * sizeof(double));
     L.end = o;
@@ -587,14 +592,27 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
     const size_t set_stride = align_up(red_count_for(p.n, p.lc) * sizeof(double)) / sizeof(double);
     int nbs = 0;  // partial blocks of the adjoint source pass (the same for every step)
     double* scratch = (double*)(ws + L.scratch);
-    // forward sweep, storing the state at the start of every segment
-    void* cur = state(L.seg, 0);
-    DGPE_HIP(launch_copy<T>(p, cur, psi0));
-    for (int s = 0; s < L.nckpt; ++s) {
-        const int n0 = s * K, len = std::min(K, nsteps - n0);
-        DGPE_HIP(launch_copy<T>(p, state(L.ckpt, s), cur));
-        dgpe_status stt = run_steps<T>(p, cur, len, amp + n0);
-        if (stt != DGPE_OK) return stt;
+    // K = 1: psi_n for n >= 1 in checkpoint slot n - 1, psi_0 the caller's
+    const bool all = K == 1;
+    auto kept = [&](int n) -> const void* { return n == 0 ? psi0 : state(L.ckpt, n - 1); };
+    // forward sweep, storing the state at the start of every segment (K = 1:
+    // every state, stepping out of place, and the Phi each step starts from)
+    void* cur = nullptr;
+    if (all) {
+        for (int n = 0; n < nsteps; ++n) {
+            dgpe_status stt = run_steps<T>(p, state(L.ckpt, n), 1, amp + n, nullptr, kept(n), phi_slot(n));
+            if (stt != DGPE_OK) return stt;
+        }
+        cur = state(L.ckpt, nsteps - 1);
+    } else {
+        cur = state(L.seg, 0);
+        DGPE_HIP(launch_copy<T>(p, cur, psi0));
+        for (int s = 0; s < L.nckpt; ++s) {
+            const int n0 = s * K, len = std::min(K, nsteps - n0);
+            DGPE_HIP(launch_copy<T>(p, state(L.ckpt, s), cur));
+            dgpe_status stt = run_steps<T>(p, cur, len, amp + n0);
+            if (stt != DGPE_OK) return stt;
+        }
     }
     if (psi_final) DGPE_HIP(launch_copy<T>(p, psi_final, cur));
     const double dV = p.d[0] * p.d[1] * p.d[2];
@@ -624,8 +642,34 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
         const double coef[2] = {2.0 * dV * cr, 2.0 * dV * ci};
         DGPE_HIP(launch_overlap_seed<T>(p, lam, target, coef));
     }
+    // one reverse step: the conjugate sweeps, the adjoint source and its
+    // convolution, the nonlinear adjoint update; source sums into partial set i
+    auto reverse_step = [&](int n, const void* psin, const void* phin, int i) -> dgpe_status {
+        DGPE_HIP(launch_cn_z<T>(p, lam, true));
+        DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
+        DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));
+        DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part + set_stride * i, &nbs));
+        DGPE_HIP(launch_rows<T>(p, false));
+        DGPE_HIP(launch_xmul<T>(p));
+        DGPE_HIP(launch_rows<T>(p, true));
+        if (!(p.fast && fast_c2r_adjupd<T>(p, lam, psin, phin, amp[n]))) {
+            DGPE_HIP(launch_c2r_phi<T>(p, phis));
+            DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
+        }
+        DGPE_HIP(hipGetLastError());
+        return DGPE_OK;
+    };
+    if (all) {
+        // every state and its Phi kept: no recompute; the source sums of all
+        // steps reduced in one launch (one block per step)
+        for (int n = nsteps - 1; n >= 0; --n) {
+            dgpe_status stt = reverse_step(n, kept(n), phi_slot(n), n);
+            if (stt != DGPE_OK) return stt;
+        }
+        DGPE_HIP(launch_reduce(p, part, nbs, 4, sums, nullptr, nsteps, set_stride));
+    }
     // reverse sweep over segments
-    for (int s = L.nckpt - 1; s >= 0; --s) {
+    for (int s = all ? -1 : L.nckpt - 1; s >= 0; --s) {
         const int n0 = s * K, len = std::min(K, nsteps - n0);
         DGPE_HIP(launch_copy<T>(p, state(L.seg, 0), state(L.ckpt, s)));
         // recompute the segment out of place; each step also leaves Phi of
@@ -636,7 +680,6 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
             if (stt != DGPE_OK) return stt;
         }
         for (int i = len - 1; i >= 0; --i) {
-            const int n = n0 + i;
             void* psin = state(L.seg, i);
             void* phin = phi_slot(i);
             if (i == len - 1) {  // the last state of the segment was never stepped from
@@ -644,18 +687,8 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
                 if (stt != DGPE_OK) return stt;
                 DGPE_HIP(launch_c2r_phi<T>(p, phin));
             }
-            DGPE_HIP(launch_cn_z<T>(p, lam, true));
-            DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
-            DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));
-            DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part + set_stride * i, &nbs));
-            DGPE_HIP(launch_rows<T>(p, false));
-            DGPE_HIP(launch_xmul<T>(p));
-            DGPE_HIP(launch_rows<T>(p, true));
-            if (!(p.fast && fast_c2r_adjupd<T>(p, lam, psin, phin, amp[n]))) {
-                DGPE_HIP(launch_c2r_phi<T>(p, phis));
-                DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
-            }
-            DGPE_HIP(hipGetLastError());
+            dgpe_status stt = reverse_step(n0 + i, psin, phin, i);
+            if (stt != DGPE_OK) return stt;
         }
         // the segment's source sums, one reduction block per step
         DGPE_HIP(launch_reduce(p, part, nbs, 4, sums + (size_t)n0 * 4, nullptr, len, set_stride));

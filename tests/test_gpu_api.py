@@ -106,11 +106,12 @@ def test_overlap_adjoint_matches_oracle(env, prec):
     assert max(errs) < (1e-10 if prec == "f64" else 5e-5)
 
 
+@pytest.mark.parametrize("ckpt", [3, 1], ids=["ckpt3", "keep_all"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [((8, 32, 64), (0.45, 0.3, 0.2)), ((6, 32, 128), (0.5, 0.3, 0.1)),
                                    ((8, 32, 256), (0.45, 0.3, 0.1))],
                          ids=lambda s: "x".join(map(str, s[0])))
-def test_adjoint_with_compiled_z_passes_matches_oracle(env, shape, prec):
+def test_adjoint_with_compiled_z_passes_matches_oracle(env, shape, prec, ckpt):
     """z lines of 64, 128 and 256 points and 32 y lines take the compiled z
     passes of the adjoint (the recompute steps' fused z pass that keeps Phi, the
     adjoint-source R2C, the C2R fused with the nonlinear adjoint update, and the
@@ -124,7 +125,7 @@ def test_adjoint_with_compiled_z_passes_matches_oracle(env, shape, prec):
     J, psiN, dJ_da, dJ_dt, lam0 = O.adjoint_evolve(p, psi0, amp, "energy", None)
     dt = torch.complex128 if prec == "f64" else torch.complex64
     plan = dg.Plan(n, d, p.dt, p.trap, p.g, p.gd, real_time=True, dtype=dt)
-    out = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=3)
+    out = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=ckpt)
     errs = _adjoint_errors(out, J, dJ_da, dJ_dt, lam0)
     print(f"  adjoint {prec}: J {errs[0]:.2e} dJ/da {errs[1]:.2e} dJ/dtrap {errs[2]:.2e} lam0 {errs[3]:.2e}",
           flush=True)
@@ -138,7 +139,7 @@ def test_adjoint_independent_of_checkpoint_interval(env):
     amp = np.random.default_rng(62).uniform(0.8, 1.2, size=14)
     plan = dg.Plan(n, d, 0.01, (1.0, 1.1, 1.6), 12.0, 6.0, real_time=True, dtype=torch.complex128)
     ref = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=13)
-    for k in (1, 4, 100):
+    for k in (1, 2, 4, 100):  # 1: every state kept, nothing recomputed
         out = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=k)
         assert out["J"] == ref["J"]
         assert np.array_equal(out["dJ_damp"], ref["dJ_damp"])
