@@ -369,7 +369,7 @@ struct PassTimer {
 template <typename T>
 bool use_fused_y(const Plan& p) {
     const size_t state = (size_t)p.n[0] * p.n[1] * p.n[2] * 2 * sizeof(T);
-    return p.fuse_y && p.fast && p.imag && p.scheme == 0 && p.n[1] / 16 <= 16 &&
+    return p.fuse_y && p.fast && p.imag && p.n[1] / 16 <= 16 &&
            state < (size_t(1) << 32) && fast_c2r_step_yfused_ok<T>(p);
 }
 
@@ -379,7 +379,7 @@ bool fused_y(const Plan& p) { return p.f32 ? use_fused_y<float>(p) : use_fused_y
 // when that pass is compiled with whole waves
 template <typename T>
 bool use_folded_norm(const Plan& p) {
-    return use_fused_y<T>(p) && fast_rows_sigma_ok<T>(p);
+    return use_fused_y<T>(p) && p.scheme == 0 && fast_rows_sigma_ok<T>(p);
 }
 
 // The nonlinear phase of the fused z pass runs over dt_nl instead of dt while
@@ -398,10 +398,14 @@ struct NonlinearStep {
 // next see the same density and run as one phase over dt (trap amplitude the
 // mean of the two steps'); the last step's trailing half is a pass of its own.
 // In imaginary time each trailing half convolves the density after the sweeps
-// and reduces the norm of its result (applied lazily by the next step).
+// and reduces the norm of its result (applied lazily by the next step); the
+// sweeps take the fused y schedule where the plan has it (the y solve started
+// in the fused z pass, completed by the carry pass and the x sweep).
 template <typename T>
 dgpe_status run_steps_strang(Plan& p, void* psi, int nsteps, const double* amp, PassTimer& t) {
     double* sigma = p.scal;
+    void* car = use_fused_y<T>(p) ? p.phi : nullptr;
+    const size_t car_bytes = (size_t)p.n[0] * (p.n[1] / 16) * p.n[2] * 2 * sizeof(T);  // one array
     for (int s = 0; s < nsteps; ++s) {
         const double a = amp ? amp[s] : 1.0;
         const double* sg = (p.imag && s > 0) ? sigma : nullptr;
@@ -413,16 +417,25 @@ dgpe_status run_steps_strang(Plan& p, void* psi, int nsteps, const double* amp, 
         if (has_y(p)) DGPE_PASS(t, 3, (launch_rows<T>(p, true)));
         {
             NonlinearStep half(p, merged ? p.dt : 0.5 * p.dt);
-            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, psi, psi, sg, a_nl)));
+            DGPE_PASS(t, 4, (launch_c2r_step<T>(p, psi, psi, sg, a_nl, nullptr, car)));
         }
-        if (has_y(p)) DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
-        DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, nullptr)));
+        if (car) {
+            DGPE_PASS(t, 5, (launch_cn_ycarry<T>(p, car)));
+            DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, nullptr, (char*)car + 3 * car_bytes)));
+        } else {
+            if (has_y(p)) DGPE_PASS(t, 5, (launch_cn_strided<T>(p, psi, 1, false, nullptr)));
+            DGPE_PASS(t, 6, (launch_cn_strided<T>(p, psi, 0, false, nullptr)));
+        }
         if (p.imag || s + 1 == nsteps) {  // the trailing half as a pass of its own
             dgpe_status st = convolve_density<T>(p, psi, nullptr);
             if (st != DGPE_OK) return st;
-            DGPE_HIP(launch_c2r_phi<T>(p, p.phi));
             int nb = 0;
-            DGPE_HIP(launch_nonlinear<T>(p, psi, p.phi, 0.5 * p.dt, a, p.red, &nb));
+            // the C2R of Phi fused with the pointwise step where compiled
+            if (!(p.fast && fast_c2r_nl<T>(p, psi, 0.5 * p.dt, a, p.red, &nb))) {
+                DGPE_HIP(launch_c2r_phi<T>(p, p.phi));
+                DGPE_HIP(launch_nonlinear<T>(p, psi, p.phi, 0.5 * p.dt, a, p.red, &nb));
+            }
+            DGPE_HIP(hipGetLastError());
             if (p.imag) DGPE_PASS(t, 7, (launch_norm_finalize(p, p.red, nb, sigma)));
         }
     }

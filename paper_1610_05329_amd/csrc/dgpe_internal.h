@@ -182,6 +182,11 @@ template <typename T>
 bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp);
 template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
+// the C2R of Phi fused with the pointwise half step of the symmetric scheme
+// (psi in place, over dt; imaginary time: block norm partials); false when the
+// grid has no compiled pass (the caller then runs the C2R and the pointwise pass)
+template <typename T>
+bool fast_c2r_nl(const Plan& p, void* psi, double dt, double amp, double* partials, int* nblocks);
 template <typename T>
 bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const double* sigma,
                    double amp, void* phi_out, void* ycar, bool phi_sigma);

@@ -628,6 +628,100 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     }
 }
 
+// The symmetric step's half nonlinear step after the sweeps, fused with the
+// C2R of Phi (its density's convolution, in the spectrum buffer):
+// psi <- psi e^{-theta} (imaginary time) or psi e^{-i theta} (real time),
+// theta = dt (a V + g |psi|^2 + g_d Phi); Phi stays in LDS, the state moves in
+// coalesced 16-byte units over the block's NB lines; in imaginary time the
+// block's FP64 sum of |psi|^2 of the result goes to partials[blockIdx.x].
+template <typename T, int R1, int R2, bool IMAG>
+__global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
+    k_c2r_nl2(cx<T>* __restrict__ psi, const cx<T>* __restrict__ spec, int Nx, int Ny,
+              const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c, Phys2 ph,
+              double* __restrict__ partials) {
+    constexpr int M = R1 * R2;
+    constexpr int Nz = 2 * M;
+    constexpr int NB = rows_per_block<T, R1, M>();
+    constexpr int NT = NB * R1;
+    constexpr int PS = M + M / 8 + 1;
+    constexpr int U = 16 / (int)sizeof(cx<T>);
+    constexpr int NU = NB * Nz / (NT * U);
+    static_assert(NU * NT * U == NB * Nz, "whole units");
+    constexpr int REG = c2r_region<R1, R2, NB>() > NB * PS ? c2r_region<R1, R2, NB>() : NB * PS;
+    __shared__ cx<T> reg[REG];
+    __shared__ cx<T> stw[M];
+    __shared__ cx<T> sr2c[M + 1];
+    __shared__ double red[NT / 64];
+    const int tid = threadIdx.x;
+    const int ngy = Ny / NB;
+    const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int x = bid / ngy;
+    const int y0 = (bid - x * ngy) * NB;
+    const size_t line0 = (size_t)x * Ny + y0;
+    TabRegs<cx<T>, M, NT> rtw;
+    TabRegs<cx<T>, M + 1, NT> rr2;
+    SpecRegs<T, M, NB, NT> rs;
+    tab_issue(rtw, twz, tid);
+    tab_issue(rr2, twr2c, tid);
+    c2r_issue_loads(rs, spec, (size_t)Nx * Ny, line0, tid);
+    // the state, issued last: in flight through the inverse transform
+    const size_t base = line0 * Nz;
+    cx<T> u[NU * U];
+#pragma unroll
+    for (int i = 0; i < NU; ++i) load_unit<T>(psi + base + (i * NT + tid) * U, u + i * U);
+    tab_stage(rtw, stw, tid, [](int i) { return i; });
+    tab_stage(rr2, sr2c, tid, [](int i) { return i; });
+    c2r_stage(rs, reg, tid);
+    __syncthreads();
+    cx<T> w[R1];
+    c2r_front2<T, R1, R2, NB>(w, reg, reg, stw, sr2c, tid);
+    __syncthreads();  // reg is rewritten with the Phi pairs
+    {
+        const int t = tid % R1, b = tid / R1;
+        if (t < R2) {
+#pragma unroll
+            for (int k = 0; k < R1; ++k) {
+                const int m = t + R2 * k;
+                reg[b * PS + m + (m >> 3)] = w[k];
+            }
+        }
+    }
+    __syncthreads();
+    const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
+    const T xx = T(x - ph.hx) * T(ph.dx);
+    const T vx = T(ph.cx) * xx * xx;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        const int e = (i * NT + tid) * U;
+        const int b = e / Nz;
+        const T yy = T(y0 + b - ph.hy) * T(ph.dy);
+        const T vxy = vx + T(ph.cy) * yy * yy;
+        cx<T> o[U];
+#pragma unroll
+        for (int v = 0; v < U; ++v) {
+            const int iz = e % Nz + v;
+            const int mm = iz >> 1;
+            const cx<T> fs = reg[b * PS + mm + (mm >> 3)];
+            const T phi = (iz & 1) ? fs.y : fs.x;
+            const T z = T(iz - ph.hz) * T(ph.dz);
+            const cx<T> q = u[i * U + v];
+            const T th = dt * (amp * (vxy + T(ph.cz) * z * z) + gg * abs2(q) + gdd * phi);
+            if constexpr (IMAG) {
+                o[v] = exp_of(-th) * q;
+                acc += double(o[v].x) * o[v].x + double(o[v].y) * o[v].y;
+            } else {
+                o[v] = rotate_phase(q, th);
+            }
+        }
+        store_unit<T>(psi + base + e, o);
+    }
+    if constexpr (IMAG) {
+        const double sum = block_sum(acc, red);
+        if (tid == 0) partials[blockIdx.x] = sum;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P5: z inverse transform -> Phi, nonlinear phase, Crank-Nicolson along z.
 // LDS: region (xin / xb, then Phi pairs, then the z carries) | Psi tile |
@@ -1125,6 +1219,37 @@ bool fast_c2r_phi(const Plan& p, void* phi) {
     }
 }
 
+template <typename T>
+bool fast_c2r_nl(const Plan& p, void* psi, double dt, double amp, double* partials, int* nblocks) {
+    const int M = p.n[2] / 2;
+    const Split2 s = fast_split(M);
+    if (!s.r1) return false;
+    const int nb = fast_rows_per_block<T>(M);
+    if (p.n[1] % nb) return false;
+    const int blocks = p.n[0] * (p.n[1] / nb);
+    if ((size_t)blocks > p.red_count) return false;
+    *nblocks = blocks;
+    Phys2 ph{dt, p.g, p.gd, amp, p.imag ? 1 : 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
+             p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
+             0.5 * p.trap[2] * p.trap[2]};
+    switch (M) {
+#define DGPE_CASE(A, B)                                                                              \
+    case A * B:                                                                                      \
+        if (p.imag)                                                                                  \
+            hipLaunchKernelGGL((k_c2r_nl2<T, A, B, true>), dim3(blocks), dim3(nb * A), 0, p.stream, \
+                               (cx<T>*)psi, (const cx<T>*)p.spec, p.n[0], p.n[1],                   \
+                               (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, ph, partials);         \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_c2r_nl2<T, A, B, false>), dim3(blocks), dim3(nb * A), 0,           \
+                               p.stream, (cx<T>*)psi, (const cx<T>*)p.spec, p.n[0], p.n[1],         \
+                               (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, ph, partials);         \
+        return true;
+        DGPE_SPLITS(DGPE_CASE)
+#undef DGPE_CASE
+        default: return false;
+    }
+}
+
 // fused P5 for Nz/2 in {32, 64, 128} with 16-point z segments
 #define DGPE_STEP_SPLITS(X) X(8, 4) X(8, 8) X(16, 8)
 
@@ -1205,6 +1330,7 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
     template bool fast_r2c_adj<T>(const Plan&, const void*, const void*, const void*, double, \
                                   double*, int*);                   \
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
+    template bool fast_c2r_nl<T>(const Plan&, void*, double, double, double*, int*); \
     template bool fast_c2r_adjupd<T>(const Plan&, void*, const void*, const void*, double); \
     template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*, \
                                    void*, bool);                                                  \
