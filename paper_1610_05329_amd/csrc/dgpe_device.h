@@ -835,44 +835,37 @@ __device__ __forceinline__ void affine_scan_down(cx<A>& a, cx<A>& b, int seg) {
 // Neighbour values and carries move by DPP row shifts, and the carry
 // recurrences d_end(k) = dtilde_end(k) + Pend(k) d_end(k-1) (and the backward
 // one) are evaluated as inclusive scans of affine maps in log2(NSEG) steps.
-// No LDS and no barriers.  Tables: alpha, P, and Q or G (length N; ta, tp, tq
-// point at this segment's S entries), pend, qbeg and H (per segment).
-// Values stored narrower than the arithmetic (FP32 state, FP64 real-time
-// recurrences) are rounded once: the back substitution runs once, from the
-// true x after the segment, and the segment's first x from a zero right
-// carry, which the backward scan needs, is accumulated in the forward pass,
-// x_first = sum_i G_i d_i = sum_i G_i dloc_i + H c_left (tq then holds G).
-template <typename T, int S, int NSEG, bool RC, typename TT, typename TS, typename VS>
-__device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
+// No LDS and no barriers.  Tables: alpha, P, Q (length N; ta, tp, tq point at
+// this segment's S entries), pend and qbeg (per segment).  The segment values
+// are held in the arithmetic type (holding the FP64 real-time values in FP32
+// saves registers the pass cannot use, its occupancy being set by LDS, and
+// costs conversions: measured slower).
+template <typename T, int S, int NSEG, bool RC, typename TT, typename TS>
+__device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S],
                                                       cx<cn_acc_t<T, RC>> kappa, const TT* ta,
                                                       const TT* tp, const TT* tq, const TS* pend,
-                                                      const TS* qbeg, int seg,
-                                                      const TS* hs = nullptr) {
+                                                      const TS* qbeg, int seg) {
     static_assert(NSEG >= 1 && NSEG <= 16 && (NSEG & (NSEG - 1)) == 0, "segments inside a row");
     using A = cn_acc_t<T, RC>;
-    constexpr bool kNarrow = sizeof(VS) < sizeof(A);
     const cx<A> zero = {A(0), A(0)};
     // neighbours
     cx<A> left = zero, right = zero;
     if constexpr (NSEG > 1) {
-        left = widen<A>(row_up<1>(v[S - 1]));
-        right = widen<A>(row_down<1>(v[0]));
+        left = row_up<1>(v[S - 1]);
+        right = row_down<1>(v[0]);
         if (seg == 0) left = zero;
         if (seg == NSEG - 1) right = zero;
     }
     // forward recurrence from a zero carry, r'_i = u_{i-1} + u_{i+1} + kappa u_i
     // formed on the fly from the input values
-    cx<A> dcur = zero, xacc = zero;
+    cx<A> dcur = zero;
     {
-        cx<A> prev = left, cur = widen<A>(v[0]);
+        cx<A> prev = left, cur = v[0];
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-            const cx<A> nxt = (i + 1 < S) ? widen<A>(v[(i + 1 < S) ? i + 1 : i]) : right;
+            const cx<A> nxt = (i + 1 < S) ? v[(i + 1 < S) ? i + 1 : i] : right;
             dcur = kmul<RC>(widen<A>(ta[i]), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
-            v[i] = to_store<VS>(dcur);
-            // narrow storage: rounded here, so that the wide value dies (the
-            // scheduler otherwise keeps all S wide values live through the scan)
-            if constexpr (kNarrow) asm volatile("" : "+v"(v[i].x), "+v"(v[i].y));
+            v[i] = dcur;
             prev = cur;
             cur = nxt;
         }
@@ -886,28 +879,15 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
         c = row_up<1>(b);
         if (seg == 0) c = zero;
     }
-    // FP64 factors are read again below rather than kept live since the
-    // forward pass (64 registers)
+    // P correction and back substitution from a zero carry.  FP64 factors are
+    // read again here rather than kept live since the forward pass (64 registers)
     if constexpr (sizeof(A) == 8) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // the segment's first x from a zero right carry
     cx<A> xcur = zero;
-    if constexpr (kNarrow) {
-        // the G entries are read after the scan (a zero offset that depends on
-        // its result keeps the scheduler from hoisting the reads and holding
-        // them through it)
-        int o = 0;
-        asm volatile("" : "+v"(o) : "v"(c.x));
 #pragma unroll
-        for (int i = 0; i < S; ++i) xacc = xacc + kmul<RC>(widen<A>(tq[o + i]), widen<A>(v[i]));
-        xcur = xacc + kmul<RC>(widen<A>(hs[seg]), c);
-    } else {
-        // P correction and back substitution from a zero carry
-#pragma unroll
-        for (int i = S - 1; i >= 0; --i) {
-            const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[i]), c);
-            xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
-            v[i] = to_store<VS>(xcur);
-        }
+    for (int i = S - 1; i >= 0; --i) {
+        const cx<A> d = v[i] + kmul<RC>(widen<A>(tp[i]), c);
+        xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
+        v[i] = xcur;
     }
     // backward scan: true x at the start of each segment; the right
     // neighbour's is the true x after the segment
@@ -919,22 +899,8 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<VS> (&v)[S],
         cr = row_down<1>(b);
         if (seg == NSEG - 1) cr = zero;
     }
-    if constexpr (kNarrow) {
-        // P correction and the one back substitution, from the true x after
-        // the segment (the factors read here, not held through the scans)
-        int o = 0;
-        asm volatile("" : "+v"(o) : "v"(cr.x));
-        xcur = cr;
 #pragma unroll
-        for (int i = S - 1; i >= 0; --i) {
-            const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[o + i]), c);
-            xcur = d + kmul<RC>(widen<A>(ta[o + i]), xcur);
-            v[i] = to_store<VS>(xcur);
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < S; ++i) v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[i]), cr));
-    }
+    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tq[i]), cr);
 }
 
 }  // namespace dgpe

@@ -456,10 +456,6 @@ __global__ void __launch_bounds__(256) k_cn_z2(cx<T>* __restrict__ f, int nlines
                                               const cx<double>* __restrict__ cntab,
                                               cx<double> kappa64) {
     using A = cn_acc_t<T, RC>;
-    // segments held in the state's precision between the recurrences (G and
-    // H tables in place of Q when that is narrower than the arithmetic)
-    using VT = std::conditional_t<RC, A, T>;
-    constexpr bool kNarrow = sizeof(VT) < sizeof(A);
     constexpr int SZ = 16;
     constexpr int NT = 256, NW = NT / 64;
     constexpr int nseg = Nz / SZ;
@@ -474,18 +470,15 @@ __global__ void __launch_bounds__(256) k_cn_z2(cx<T>* __restrict__ f, int nlines
     __shared__ cx<A> tq[TS];
     __shared__ cx<A> spe[nseg];
     __shared__ cx<A> sqb[nseg];
-    __shared__ cx<A> shh[kNarrow ? nseg : 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wl0 = (xcd_swizzle(blockIdx.x, gridDim.x) * NW + wv) * LPW;
     TabRegs<cx<double>, Nz, NT> rta, rtp, rtq;
     TabRegs<cx<double>, nseg, NT> rpe, rqb;
-    TabRegs<cx<double>, kNarrow ? nseg : 1, NT> rhh;
     tab_issue(rta, cntab + TAB_ALPHA * Nz, tid);
     tab_issue(rtp, cntab + TAB_P * Nz, tid);
-    tab_issue(rtq, cntab + (kNarrow ? TAB_G : TAB_Q) * Nz, tid);
+    tab_issue(rtq, cntab + TAB_Q * Nz, tid);
     tab_issue(rpe, cntab + TAB_PEND * Nz, tid);
     tab_issue(rqb, cntab + TAB_QBEG * Nz, tid);
-    if constexpr (kNarrow) tab_issue(rhh, cntab + TAB_H * Nz, tid);
     // waves past the last line load the last wave's lines (unused)
     cx<T>* wp = f + (size_t)min(wl0, nlines - LPW) * Nz;
     cx<T> a[SZ];
@@ -498,16 +491,15 @@ __global__ void __launch_bounds__(256) k_cn_z2(cx<T>* __restrict__ f, int nlines
     tab_stage(rtq, tq, tid, padded);
     tab_stage(rpe, spe, tid, ident);
     tab_stage(rqb, sqb, tid, ident);
-    if constexpr (kNarrow) tab_stage(rhh, shh, tid, ident);
     __syncthreads();
     if (wl0 >= nlines) return;  // no barrier follows
     cx<T>* st = stg + wv * KR * WL::SL;
     const int seg = lane % nseg;
-    cx<VT> v[SZ];
+    cx<A> v[SZ];
     WL::to_segments(st, a, v, lane);
     const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
     const int tb = seg * (SZ + 1);
-    cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg, shh);
+    cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
     WL::store_from_segments(st, v, wp, lane);
 }
 

@@ -806,11 +806,6 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
                 const cx<double>* __restrict__ ytab, cx<double> kappay64,
                 cx<T>* __restrict__ ycar, int phi_sigma) {
     using A = cn_acc_t<T, RC>;
-    // the z segments are held in the state's precision between the
-    // recurrences (FP32 real time: FP64 arithmetic on FP32 values, the G and H
-    // tables in place of Q; see cn_segment_solve_wave)
-    using VT = std::conditional_t<RC, A, T>;
-    constexpr bool kNarrow = sizeof(VT) < sizeof(A);
     using G = Step2Geom<T, R1, R2, SZ>;
     constexpr int M = G::M, Nz = G::Nz, nseg = G::nseg, LPW = G::LPW, U = G::U, NU = G::NU;
     constexpr int PS = G::PS, SL = G::SL, KR = G::KR, JR = G::JR;
@@ -831,7 +826,6 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     __shared__ cx<A> tq[TS];
     __shared__ cx<A> spe[nseg];
     __shared__ cx<A> sqb[nseg];
-    __shared__ cx<A> shh[kNarrow ? nseg : 1];
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
     __shared__ cx<A> sya[YF ? NB : 1];
@@ -850,16 +844,14 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     TabRegs<cx<T>, M + 1, NT> rr2;
     TabRegs<cx<double>, Nz, NT> rta, rtp, rtq;
     TabRegs<cx<double>, nseg, NT> rpe, rqb;
-    TabRegs<cx<double>, kNarrow ? nseg : 1, NT> rhh;
     SpecRegs<T, M, NB, NT> rsp;
     tab_issue(rtw, twz, tid);
     tab_issue(rr2, twr2c, tid);
     tab_issue(rta, cntab + TAB_ALPHA * Nz, tid);
     tab_issue(rtp, cntab + TAB_P * Nz, tid);
-    tab_issue(rtq, cntab + (kNarrow ? TAB_G : TAB_Q) * Nz, tid);
+    tab_issue(rtq, cntab + TAB_Q * Nz, tid);
     tab_issue(rpe, cntab + TAB_PEND * Nz, tid);
     tab_issue(rqb, cntab + TAB_QBEG * Nz, tid);
-    if constexpr (kNarrow) tab_issue(rhh, cntab + TAB_H * Nz, tid);
     TabRegs<cx<double>, YF ? NB : 1, NT> rya;
     if constexpr (YF) tab_issue(rya, ytab + TAB_ALPHA * Ny + y0, tid);
     c2r_issue_loads(rsp, spec, (size_t)Nx * Ny, line0, tid);
@@ -879,7 +871,6 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     tab_stage(rtq, tq, tid, padded);
     tab_stage(rpe, spe, tid, ident);
     tab_stage(rqb, sqb, tid, ident);
-    if constexpr (kNarrow) tab_stage(rhh, shh, tid, ident);
     if constexpr (YF) tab_stage(rya, sya, tid, ident);
     c2r_stage(rsp, reg, tid);
     __syncthreads();
@@ -899,7 +890,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     __syncthreads();
     if (!YF && !act) return;  // no barrier follows (YF: the y phase has barriers)
     const int seg = lane % nseg;
-    cx<VT> v[SZ];
+    cx<A> v[SZ];
     if (act) {
     // nonlinear step in the load layout (pre-step density, lazily normalised).
     // The exponent is a line term (x, y) plus a z term, shared by the points
@@ -958,7 +949,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     // lanes of one wave (carries by shuffles)
     const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
     const int tb = seg * (SZ + 1);
-    cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg, shh);
+    cn_segment_solve_wave<T, SZ, nseg, RC>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
     // back to the load layout and out
     if constexpr (!YF) WaveLines<T, Nz, SZ, KR>::store_from_segments(stg, v, psi_out + wl, lane);
     }  // act
