@@ -767,7 +767,11 @@ struct Step2Geom {
     static constexpr int LPW = 64 / nseg;
     static constexpr int U = 16 / (int)sizeof(cx<T>);
     static constexpr int NU = SZ / U;  // units per lane
-    static constexpr int PS = M + M / 8 + 1;
+    // Phi pairs at m + (m >> PSH): one pad entry per 8 (FP32) or 16 (FP64, 16-byte
+    // entries) spreads the reads over the banks; the smaller FP64 pad keeps the
+    // block within 53 KB of LDS, three blocks per CU
+    static constexpr int PSH = sizeof(T) == 8 ? 4 : 3;
+    static constexpr int PS = M + (M >> PSH) + 1;
     static constexpr int SL = Nz + nseg * U;
     static constexpr int fit = (LPW * PS) / SL;
     static constexpr int KR = fit >= LPW ? LPW : fit >= 8 ? 8 : fit >= 4 ? 4 : fit >= 2 ? 2 : 1;
@@ -808,7 +812,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     using A = cn_acc_t<T, RC>;
     using G = Step2Geom<T, R1, R2, SZ>;
     constexpr int M = G::M, Nz = G::Nz, nseg = G::nseg, LPW = G::LPW, U = G::U, NU = G::NU;
-    constexpr int PS = G::PS, SL = G::SL, KR = G::KR, JR = G::JR;
+    constexpr int PS = G::PS, SL = G::SL, KR = G::KR, JR = G::JR, PSH = G::PSH;
     constexpr int NB = step2_nb<T, R1, R2, SZ>();
     constexpr int NT = step2_threads<T, R1, R2, SZ>();
     static_assert(Nz % SZ == 0 && SZ % U == 0, "full segments of whole units");
@@ -817,7 +821,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
     static_assert(LPW % KR == 0 && (KR * Nz) % (64 * U) == 0 && KR * SL <= LPW * PS,
                   "staging rounds of whole unit loads inside the wave's Phi rows");
     static_assert((LPW * PS) % U == 0, "16-byte aligned staging");
-    // Phi pairs at m + m/8 and table entries at e + e/SZ (bank spread)
+    // Phi pairs at m + (m >> PSH) and table entries at e + e/SZ (bank spread)
     constexpr int TS = Nz + Nz / SZ;
     constexpr int REG = c2r_region<R1, R2, NB>() > NB * PS ? c2r_region<R1, R2, NB>() : NB * PS;
     __shared__ __align__(16) cx<T> reg[REG];
@@ -883,7 +887,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
 #pragma unroll
             for (int k = 0; k < R1; ++k) {
                 const int m = t + R2 * k;
-                reg[b * PS + m + (m >> 3)] = w[k];
+                reg[b * PS + m + (m >> PSH)] = w[k];
             }
         }
     }
@@ -919,7 +923,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
         const int iy = iy0 + lw;
         const T cl = ky * T(iy * iy) + cx0;
         const int m = e0 >> 1;
-        const cx<T> fv = prow[lw * PS + m + (m >> 3)];
+        const cx<T> fv = prow[lw * PS + m + (m >> PSH)];
         if constexpr (PHI) {  // Phi of the pre-step density, for the adjoint
             const T phs = phi_sigma ? T(sg) : T(1);
             if constexpr (U == 2) *reinterpret_cast<cx<T>*>(phi_out + wl + c0) = phs * fv;
