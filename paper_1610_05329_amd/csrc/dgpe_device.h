@@ -123,23 +123,26 @@ __device__ __forceinline__ void sin_cos(T x, T* s, T* c) {
     detail::quadrant(q, sr, T(1) + cm1r, s, c);
 }
 
-// psi e^{-i theta}, formed as psi + psi (e^{-i theta} - 1) with cos theta - 1
-// taken from its series without the leading 1 in the first quadrant (in the
-// others |cos theta - 1| >= 1 - 1/sqrt 2 and c - 1 loses nothing).  cos theta
-// itself, rounded to the state's precision near theta = 0, is off by up to half
-// an ulp of 1 with one sign over neighbouring points and steps: |e^{-i theta}|
-// then differs from 1 by about that much and the real-time norm drifts.  The
-// increment psi (e^{-i theta} - 1) keeps its full relative precision, so the
-// modulus error is of order theta^2 eps, and the result is rounded once.
+// psi e^{-i theta} with theta = r + q pi/2, |r| <= pi/4: first the q quarter
+// turns, (-i)^q psi, exactly (a swap of the components and sign changes), then
+// the small angle as p + p (e^{-i r} - 1) with sin r and cos r - 1 from their
+// series (cos r - 1 without the leading 1).  cos r itself, rounded to the
+// state's precision near r = 0, is off by up to half an ulp of 1 with one sign
+// over neighbouring points and steps: |e^{-i theta}| would then differ from 1
+// by about that much and the real-time norm drift.  The increment keeps its
+// full relative precision, so the modulus error is of order r^2 eps, and the
+// result is rounded once.
 template <typename T>
 __device__ __forceinline__ cx<T> rotate_phase(cx<T> q, T th) {
     int qd;
     T sr, cm1r;
     sin_cosm1_reduced(th, &qd, &sr, &cm1r);
-    T s, c;
-    detail::quadrant(qd, sr, T(1) + cm1r, &s, &c);
-    const T cm1 = qd == 0 ? cm1r : c - T(1);
-    return cx<T>{q.x + fma(q.y, s, q.x * cm1), q.y + fma(-q.x, s, q.y * cm1)};
+    // (-i)^q (x + i y): q = 1 (y, -x), 2 (-x, -y), 3 (-y, x)
+    T a = (qd & 1) ? q.y : q.x;
+    T b = (qd & 1) ? q.x : q.y;
+    if (qd & 2) a = -a;
+    if ((qd + 1) & 2) b = -b;
+    return cx<T>{a + fma(b, sr, a * cm1r), b + fma(-a, sr, b * cm1r)};
 }
 
 // exp(x) = 2^(x log2 e) on the hardware base-2 exponential (v_exp_f32, about
@@ -393,6 +396,14 @@ template <bool RC, typename T>
 __device__ __forceinline__ cx<T> kmul(cx<T> k, cx<T> a) {
     if constexpr (RC) return cx<T>{k.x * a.x, k.x * a.y};
     else return cmul(k, a);
+}
+// c + k a, the products accumulated by fused multiply-adds (two per component
+// for complex k, one for real k): the recurrences' multiply-then-add steps in
+// half the instructions
+template <bool RC, typename T>
+__device__ __forceinline__ cx<T> kfma(cx<T> k, cx<T> a, cx<T> c) {
+    if constexpr (RC) return cx<T>{fma(k.x, a.x, c.x), fma(k.x, a.y, c.y)};
+    else return cx<T>{fma(k.x, a.x, fma(-k.y, a.y, c.x)), fma(k.x, a.y, fma(k.y, a.x, c.y))};
 }
 
 // Arithmetic type of the tridiagonal recurrences: the storage type in
@@ -649,11 +660,11 @@ __device__ __forceinline__ cx<A> carry_chain(const cx<A>* buf, const cx<A>* m, i
             mv[q] = m[k];
         }
 #pragma unroll
-        for (int q = 0; q < CH; ++q) c = bv[q] + kmul<RC>(mv[q], c);
+        for (int q = 0; q < CH; ++q) c = kfma<RC>(mv[q], c, bv[q]);
     }
     for (; r < n; ++r) {
         const int k = REV ? k1 - 1 - r : k0 + r;
-        c = buf[k * nlines + line] + kmul<RC>(m[k], c);
+        c = kfma<RC>(m[k], c, buf[k * nlines + line]);
     }
     return c;
 }
@@ -710,10 +721,10 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
                 if (!GUARD || i + 1 < cnt) nxt = widen<A>(v[(i + 1 < S) ? i + 1 : i]);
             }
             if (!GUARD || i < cnt) {
-                dcur = kmul<RC>(alpha(i), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
+                dcur = kmul<RC>(alpha(i), kfma<RC>(kappa, cur, (dcur + prev) + nxt));
                 v[i] = to_store<VS>(dcur);
                 // the segment's first x from zero carries on both sides
-                if constexpr (kTwice) xacc = xacc + kmul<RC>(widen<A>(tg[tb + i]), dcur);
+                if constexpr (kTwice) xacc = kfma<RC>(widen<A>(tg[tb + i]), dcur, xacc);
             }
             prev = cur;
             cur = nxt;
@@ -727,14 +738,14 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
         // left (P correction), then back substitution from a zero carry
         c = carry_chain<A, RC, false>(dl, pend, 0, seg, nlines, line);
         if constexpr (kTwice) {
-            xf[seg * nlines + line] = xacc + kmul<RC>(widen<A>(hs[seg]), c);
+            xf[seg * nlines + line] = kfma<RC>(widen<A>(hs[seg]), c, xacc);
         } else {
             cx<A> xcur = {A(0), A(0)};
 #pragma unroll
             for (int i = S - 1; i >= 0; --i) {
                 if (!GUARD || i < cnt) {
-                    const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
-                    xcur = d + kmul<RC>(alpha(i), xcur);
+                    const cx<A> d = kfma<RC>(widen<A>(tp[tb + i]), c, widen<A>(v[i]));
+                    xcur = kfma<RC>(alpha(i), xcur, d);
                     v[i] = to_store<VS>(xcur);
                 }
             }
@@ -752,8 +763,8 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
 #pragma unroll
             for (int i = S - 1; i >= 0; --i) {
                 if (!GUARD || i < cnt) {
-                    const cx<A> d = widen<A>(v[i]) + kmul<RC>(widen<A>(tp[tb + i]), c);
-                    xcur = d + kmul<RC>(alpha(i), xcur);
+                    const cx<A> d = kfma<RC>(widen<A>(tp[tb + i]), c, widen<A>(v[i]));
+                    xcur = kfma<RC>(alpha(i), xcur, d);
                     v[i] = to_store<VS>(xcur);
                 }
             }
@@ -761,7 +772,7 @@ __device__ __forceinline__ void cn_segment_solve(cx<VS> (&v)[S], int cnt,
 #pragma unroll
             for (int i = 0; i < S; ++i)
                 if (!GUARD || i < cnt)
-                    v[i] = to_store<VS>(widen<A>(v[i]) + kmul<RC>(widen<A>(tq[tb + i]), cr));
+                    v[i] = to_store<VS>(kfma<RC>(widen<A>(tq[tb + i]), cr, widen<A>(v[i])));
         }
     }
 }
@@ -811,7 +822,7 @@ __device__ __forceinline__ void affine_scan_up(cx<A>& a, cx<A>& b, int seg) {
     if constexpr (O < NSEG) {
         const cx<A> ap = row_up<O>(a), bp = row_up<O>(b);
         if (seg >= O) {
-            b = b + kmul<RC>(a, bp);
+            b = kfma<RC>(a, bp, b);
             a = kmul<RC>(a, ap);
         }
         affine_scan_up<2 * O, NSEG, RC>(a, b, seg);
@@ -822,7 +833,7 @@ __device__ __forceinline__ void affine_scan_down(cx<A>& a, cx<A>& b, int seg) {
     if constexpr (O < NSEG) {
         const cx<A> ap = row_down<O>(a), bp = row_down<O>(b);
         if (seg + O < NSEG) {
-            b = b + kmul<RC>(a, bp);
+            b = kfma<RC>(a, bp, b);
             a = kmul<RC>(a, ap);
         }
         affine_scan_down<2 * O, NSEG, RC>(a, b, seg);
@@ -864,7 +875,7 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             const cx<A> nxt = (i + 1 < S) ? v[(i + 1 < S) ? i + 1 : i] : right;
-            dcur = kmul<RC>(widen<A>(ta[i]), dcur + (prev + nxt + kmul<RC>(kappa, cur)));
+            dcur = kmul<RC>(widen<A>(ta[i]), kfma<RC>(kappa, cur, (dcur + prev) + nxt));
             v[i] = dcur;
             prev = cur;
             cur = nxt;
@@ -885,8 +896,8 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
     cx<A> xcur = zero;
 #pragma unroll
     for (int i = S - 1; i >= 0; --i) {
-        const cx<A> d = v[i] + kmul<RC>(widen<A>(tp[i]), c);
-        xcur = d + kmul<RC>(widen<A>(ta[i]), xcur);
+        const cx<A> d = kfma<RC>(widen<A>(tp[i]), c, v[i]);
+        xcur = kfma<RC>(widen<A>(ta[i]), xcur, d);
         v[i] = xcur;
     }
     // backward scan: true x at the start of each segment; the right
@@ -900,7 +911,7 @@ __device__ __forceinline__ void cn_segment_solve_wave(cx<cn_acc_t<T, RC>> (&v)[S
         if (seg == NSEG - 1) cr = zero;
     }
 #pragma unroll
-    for (int i = 0; i < S; ++i) v[i] = v[i] + kmul<RC>(widen<A>(tq[i]), cr);
+    for (int i = 0; i < S; ++i) v[i] = kfma<RC>(widen<A>(tq[i]), cr, v[i]);
 }
 
 }  // namespace dgpe

@@ -150,8 +150,8 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
 #pragma unroll
         for (int i = 0; i < S; ++i)
             if (!GUARD || i < cnt)
-                v[i] = to_store<T>(widen<A>(v[i]) + kmul<RC>(ey, widen<A>(cc[i][0])) +
-                                   kmul<RC>(qy, widen<A>(cc[i][1])));
+                v[i] = to_store<T>(kfma<RC>(qy, widen<A>(cc[i][1]),
+                                            kfma<RC>(ey, widen<A>(cc[i][0]), widen<A>(v[i]))));
     }
     ta[i0 + i0 / S] = narrow_tab<A>(a0);
     tp[i0 + i0 / S] = narrow_tab<A>(p0);
@@ -269,7 +269,7 @@ __global__ void __launch_bounds__(64) k_cn_ycarry(cx<T>* __restrict__ car, int N
         if (k < K) {
             cd[k] = c;
             const cx<A> ufn = k + 1 < K ? widen<A>(uf[k + 1 < KM ? k + 1 : k]) : zero;
-            c = widen<A>(dl[k]) + kmul<RC>(sf[0][k], ufn) + kmul<RC>(sf[1][k], c);
+            c = kfma<RC>(sf[1][k], c, kfma<RC>(sf[0][k], ufn, widen<A>(dl[k])));
         }
     const int zbm = (1 << lzb) - 1;
     const size_t ktile = (size_t)(Nz >> lzb) * Nx << lzb;  // pairs per segment
@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(64) k_cn_ycarry(cx<T>* __restrict__ car, int N
     for (int k = KM - 1; k >= 0; --k)
         if (k < K) {
             const cx<A> cxk = c;
-            c = widen<A>(xf[k]) + kmul<RC>(sf[2][k], cd[k]) + kmul<RC>(sf[3][k], cxk);
+            c = kfma<RC>(sf[3][k], cxk, kfma<RC>(sf[2][k], cd[k], widen<A>(xf[k])));
             cx<T> t2[2] = {to_store<T>(cd[k]), to_store<T>(cxk)};
             if constexpr (sizeof(T) == 4) {
                 store_unit<T>(pr + (size_t)k * ktile * 2, t2);
@@ -342,7 +342,7 @@ __global__ void __launch_bounds__(64) k_cn_ycarry2(cx<T>* __restrict__ car, int 
             const int k = k0 + j;
             cd[j] = c;
             const cx<A> ufn = (k + 1 < k1) ? widen<A>(uf[j + 1 < KH ? j + 1 : j]) : ufend;
-            c = widen<A>(dl[j]) + kmul<RC>(sf[0][k], ufn) + kmul<RC>(sf[1][k], c);
+            c = kfma<RC>(sf[1][k], c, kfma<RC>(sf[0][k], ufn, widen<A>(dl[j])));
         }
     const cx<A> cin = shfl_up_c(c, 32, 64);  // the lower half's end value, on the upper lanes
     if (half) {
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(64) k_cn_ycarry2(cx<T>* __restrict__ car, int 
 #pragma unroll
         for (int j = 0; j < KH; ++j)
             if (k0 + j < k1) {
-                cd[j] = cd[j] + kmul<RC>(pp, cin);
+                cd[j] = kfma<RC>(pp, cin, cd[j]);
                 pp = kmul<RC>(sf[1][k0 + j], pp);
             }
     }
@@ -362,7 +362,7 @@ __global__ void __launch_bounds__(64) k_cn_ycarry2(cx<T>* __restrict__ car, int 
         if (k0 + j < k1) {
             const int k = k0 + j;
             cx_[j] = c;
-            c = widen<A>(xf[j]) + kmul<RC>(sf[2][k], cd[j]) + kmul<RC>(sf[3][k], c);
+            c = kfma<RC>(sf[3][k], c, kfma<RC>(sf[2][k], cd[j], widen<A>(xf[j])));
         }
     const cx<A> xin = shfl_down_c(c, 32, 64);  // the upper half's end value, on the lower lanes
     if (!half) {
@@ -370,7 +370,7 @@ __global__ void __launch_bounds__(64) k_cn_ycarry2(cx<T>* __restrict__ car, int 
 #pragma unroll
         for (int j = KH - 1; j >= 0; --j)
             if (k0 + j < k1) {
-                cx_[j] = cx_[j] + kmul<RC>(qq, xin);
+                cx_[j] = kfma<RC>(qq, xin, cx_[j]);
                 qq = kmul<RC>(sf[3][k0 + j], qq);
             }
     }

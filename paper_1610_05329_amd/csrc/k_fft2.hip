@@ -996,7 +996,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
                 for (int j = 0; j < 16; ++j) {
                     const cx<A> cur = w2[j];
                     const cx<A> nxt = j < 15 ? w2[j < 15 ? j + 1 : j] : zero;
-                    d = kmul<RC>(al[j], d + (prev + nxt + kmul<RC>(kappay, cur)));
+                    d = kmul<RC>(al[j], kfma<RC>(kappay, cur, (d + prev) + nxt));
                     prev = cur;
                     w2[j] = d;
                 }
@@ -1004,7 +1004,7 @@ __attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
                 cx<A> xv = zero;
 #pragma unroll
                 for (int j = 15; j >= 0; --j) {
-                    xv = w2[j] + kmul<RC>(al[j], xv);
+                    xv = kfma<RC>(al[j], xv, w2[j]);
                     w2[j] = xv;
                 }
                 const int z = h * HZ + col;
