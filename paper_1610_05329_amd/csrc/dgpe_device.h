@@ -784,13 +784,15 @@ namespace dgpe {
 
 // Lane shifts inside rows of 16 lanes (DPP row_shr:D, row_shl:D): lane l
 // receives lane l - D (up) or l + D (down) of its row, a lane whose source
-// lies outside its row keeps its own value.  For groups of W <= 16
-// consecutive lanes (W a power of two dividing 16) every source inside the
-// lane's group is inside its row, which is all the wave solver reads.  One
-// VALU move per 32-bit word, instead of an LDS permute.
+// lies outside its row receives 0.  For groups of W <= 16 consecutive lanes
+// (W a power of two dividing 16) every source inside the lane's group is
+// inside its row, which is all the wave solver uses: every lane whose source
+// lies outside its group discards what it receives.  One VALU move per 32-bit
+// word, instead of an LDS permute (with zero fill the move needs no copy of
+// the old value first).
 template <int CTRL>
 __device__ __forceinline__ int dpp_word(int v) {
-    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v) {
