@@ -154,11 +154,20 @@ bool choose_launch(const int n[3], bool f32, bool imag, Launch* lc) {
         // measured at 256^3: 32 columns per block (FP32 recurrences) and 16
         // (FP64 recurrences) overlap loads and solves better than 64
         int zb = narrow ? 32 : 16;
-        auto lds = [&](int z) { return (size_t)(2 * nseg * z + 3 * nseg * (S + 1) + 3 * nseg) * asz; };
-        while (zb > 1 && (C % zb || nseg * zb > tmax || lds(zb) > kLdsBudget)) zb >>= 1;
-        if (C % zb || nseg * zb > tmax || lds(zb) > kLdsMax) return false;
+        while (zb > 1 && (C % zb || nseg * zb > tmax)) zb >>= 1;
+        // the tables in LDS where they leave room for these columns; long lines
+        // read them from global memory (L1/L2 resident) instead of giving up
+        // columns (at 2048 points, FP64: 104 KB of tables left one 128-thread
+        // block of one column per CU)
+        auto lds = [&](int z, bool gt) {
+            return (size_t)(2 * nseg * z + (gt ? 0 : 3 * nseg * (S + 1)) + 3 * nseg) * asz;
+        };
+        const bool gt = lds(zb, false) > kLdsBudget;
+        while (zb > 1 && lds(zb, gt) > kLdsBudget) zb >>= 1;
+        if (C % zb || nseg * zb > tmax || lds(zb, gt) > kLdsMax) return false;
         lc->seg[axis] = S;
         lc->logZB[axis] = ilog2(zb);
+        lc->gtab[axis] = gt ? 1 : 0;
     }
     return true;
 }
@@ -180,7 +189,7 @@ size_t red_count_for(const int n[3], const Launch& lc) {
 // Computes the workspace carve-up; offs[OFF_END] is the total.
 bool layout(const int n[3], bool f32, size_t offs[OFF_END + 1], Launch* lc_out,
             bool imag = true) {
-    Launch lc;
+    Launch lc{};
     if (!choose_launch(n, f32, imag, &lc)) return false;
     Launch other;  // the workspace serves both time modes (dgpe_plan_set)
     if (!choose_launch(n, f32, !imag, &other)) return false;
@@ -775,7 +784,7 @@ dgpe_status create_plan(dgpe_plan* out, const int32_t n[3], const double d[3], d
     const bool f32 = (mode & DGPE_F32) != 0;
     int nn[3] = {n[0], n[1], n[2]};
     size_t offs[OFF_END + 1];
-    Launch lc;
+    Launch lc{};
     if (!layout(nn, f32, offs, &lc, (mode & DGPE_REAL) == 0))
         return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape fits this grid");
     dgpe_status st = check_ptr(workspace, "workspace");
@@ -980,7 +989,7 @@ dgpe_status dgpe_plan_set(dgpe_plan plan, int32_t param, double value) {
             break;
         case DGPE_PARAM_REAL_TIME: {
             if (value != 0.0 && value != 1.0) return fail(DGPE_EINVAL, "REAL_TIME takes 0 or 1");
-            Launch lc;
+            Launch lc{};
             if (!choose_launch(p.n, p.f32, value == 0.0, &lc))
                 return fail(DGPE_EUNSUPPORTED_SIZE, "no launch shape for this mode");
             p.imag = value == 0.0;

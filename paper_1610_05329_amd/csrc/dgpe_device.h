@@ -148,8 +148,8 @@ __device__ __forceinline__ cx<T> rotate_phase(cx<T> q, T th) {
 // exp(x) = 2^(x log2 e) on the hardware base-2 exponential (v_exp_f32, about
 // 1 ulp): the product's rounding adds |x| eps relative, negligible for the
 // imaginary-time factors exp(-theta), theta = dt (...) << 1, and it takes 2
-// instructions where the library expf takes about 8 (the fused z pass is
-// limited by instruction issue, not by HBM)
+// instructions where the library expf takes about 8 (instruction issue is
+// about two thirds of the fused z pass's time, next to its HBM traffic)
 __device__ __forceinline__ float exp_of(float x) {
     return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f);
 }

@@ -45,6 +45,8 @@ struct Launch {
     int logB_x;   // columns per block in the x pass
     int seg[3];   // Thomas segment length per axis
     int logZB[3]; // columns per block of the strided sweeps (x, y)
+    int gtab[3];  // strided sweeps: Thomas tables read from global memory, not
+                  // staged in LDS (lines whose tables would crowd out the columns)
 };
 
 struct Plan {

@@ -53,7 +53,10 @@ __device__ __forceinline__ cx<double> tab_at(const cx<double>* t, int i) {
 // (c_d, c_x) from the carry pass at ycar, tiled per block
 // ([Ny/16][Nz/ZB][Nx][ZB][2]: the blocks of one segment and z range read one
 // contiguous tile), and E, Q from the y tables.
-template <typename T, int S, bool RC, bool GUARD, bool YC>
+//
+// GT: the alpha, P and Q (or G) tables are read from global memory where they
+// are used (L1/L2 resident, shared by every block), not staged in LDS.
+template <typename T, int S, bool RC, bool GUARD, bool YC, bool GT>
 __global__ void __launch_bounds__(YC || sizeof(T) == 8 ? kMaxThreads / 2 : kMaxThreads)
 __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8)))
     k_cn_strided(cx<T>* __restrict__ f, int L, int C, int logZB, int nseg, CnTab tg,
@@ -66,9 +69,10 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int ZB = 1 << logZB;
     const int nsl = nseg << logZB;
+    static_assert(!(GT && YC), "the carry-completing sweep stages its tables");
     cx<A>* A1 = reinterpret_cast<cx<A>*>(smem_raw);
     cx<A>* A2 = A1 + nsl;
-    const int TL = nseg * (S + 1);
+    const int TL = GT ? 0 : nseg * (S + 1);
     cx<A>* ta = A2 + nsl;
     cx<A>* tp = ta + TL;
     cx<A>* tq = tp + TL;
@@ -83,8 +87,9 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
     // ones that store narrower the G and H tables (see cn_segment_solve); the
     // tq area holds either
     constexpr bool kQ = sizeof(T) >= sizeof(A);
-    const cx<double> a0 = tab_at<RC>(tg.a, i0), p0 = tab_at<RC>(tg.p, i0);
-    const cx<double> q0 = kQ ? tab_at<RC>(tg.q, i0) : cx<double>{0.0, 0.0};
+    const cx<double> a0 = GT ? cx<double>{0.0, 0.0} : tab_at<RC>(tg.a, i0);
+    const cx<double> p0 = GT ? cx<double>{0.0, 0.0} : tab_at<RC>(tg.p, i0);
+    const cx<double> q0 = (kQ && !GT) ? tab_at<RC>(tg.q, i0) : cx<double>{0.0, 0.0};
     const cx<double> pe0 = tab_at<RC>(tg.pend, s0), qb0 = tab_at<RC>(tg.qbeg, s0);
     const cx<A> kappa = narrow_tab<A>(kappa64);
     const int ncb = C >> logZB;
@@ -153,23 +158,27 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
                 v[i] = to_store<T>(kfma<RC>(qy, widen<A>(cc[i][1]),
                                             kfma<RC>(ey, widen<A>(cc[i][0]), widen<A>(v[i]))));
     }
-    ta[i0 + i0 / S] = narrow_tab<A>(a0);
-    tp[i0 + i0 / S] = narrow_tab<A>(p0);
     pe[s0] = narrow_tab<A>(pe0);
     qb[s0] = narrow_tab<A>(qb0);
+    if constexpr (!GT) {
+        ta[i0 + i0 / S] = narrow_tab<A>(a0);
+        tp[i0 + i0 / S] = narrow_tab<A>(p0);
+    }
     if constexpr (kQ) {
-        tq[i0 + i0 / S] = narrow_tab<A>(q0);
+        if constexpr (!GT) tq[i0 + i0 / S] = narrow_tab<A>(q0);
     } else {
         // G and H are first read after the neighbour exchange below, which
         // waits for the state anyway: loaded after it (registers)
-        tq[i0 + i0 / S] = narrow_tab<A>(tab_at<RC>(tg.g, i0));
+        if constexpr (!GT) tq[i0 + i0 / S] = narrow_tab<A>(tab_at<RC>(tg.g, i0));
         hs[s0] = narrow_tab<A>(tab_at<RC>(tg.h, s0));
     }
-    for (int i = tid + nthr; i < L; i += nthr) {  // lines longer than the block
-        const int ip = i + i / S;
-        ta[ip] = narrow_tab<A>(tg.a[i]);
-        tp[ip] = narrow_tab<A>(tg.p[i]);
-        tq[ip] = narrow_tab<A>(kQ ? tg.q[i] : tg.g[i]);
+    if constexpr (!GT) {
+        for (int i = tid + nthr; i < L; i += nthr) {  // lines longer than the block
+            const int ip = i + i / S;
+            ta[ip] = narrow_tab<A>(tg.a[i]);
+            tp[ip] = narrow_tab<A>(tg.p[i]);
+            tq[ip] = narrow_tab<A>(kQ ? tg.q[i] : tg.g[i]);
+        }
     }
     for (int i = tid + nthr; i < nseg; i += nthr) {
         pe[i] = narrow_tab<A>(tg.pend[i]);
@@ -193,8 +202,14 @@ __attribute__((amdgpu_waves_per_eu(YC && sizeof(cn_acc_t<T, RC>) == 4 ? 4 : 1, 8
         if (seg + 1 < nseg) right = A1[(seg + 1) * ZB + cl];
     }
     __syncthreads();  // neighbour reads done: A2 becomes the forward carries, A1 the backward ones
-    cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta, tp, tq, pe, qb, seg * (S + 1), seg,
-                                      nseg, A2, A1, cl, ZB, tq, hs);
+    if constexpr (GT) {
+        const cx<double>* gq = kQ ? tg.q : tg.g;
+        cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, tg.a, tg.p, gq, pe, qb, e0, seg,
+                                          nseg, A2, A1, cl, ZB, gq, hs);
+    } else {
+        cn_segment_solve<T, S, RC, GUARD>(v, cnt, left, right, kappa, ta, tp, tq, pe, qb, seg * (S + 1),
+                                          seg, nseg, A2, A1, cl, ZB, tq, hs);
+    }
     double acc = 0.0;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
@@ -547,11 +562,18 @@ hipError_t launch_cn_strided(const Plan& p, void* f, int axis, bool conjugate,
     const cx<double> kappa = {k.re, k.im};
     const int blocks = cn_strided_blocks(p, axis, ycar != nullptr);
     const size_t asz = (p.imag ? sizeof(T) : sizeof(double)) * 2;
-    const size_t sm = (size_t)(2 * threads + 3 * nseg * (S + 1) + 3 * nseg) * asz;
+    // the carry-completing sweep stages its tables (lines it takes fit)
+    const bool gt = p.lc.gtab[axis] && !ycar;
+    const size_t sm = (size_t)(2 * threads + (gt ? 0 : 3 * nseg * (S + 1)) + 3 * nseg) * asz;
     const bool guard = (L % S) != 0;
     const cx<double>* ytab = (const cx<double>*)p.cntab[1][0];
 #define DGPE_CN(SV, RCV, GV, YV)                                                                      \
-    hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV, YV>), dim3(blocks), dim3(threads), sm, p.stream, \
+    if (gt && !YV)                                                                                    \
+        hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV, false, true>), dim3(blocks), dim3(threads),  \
+                           sm, p.stream, (cx<T>*)f, L, C, logZB, nseg, tg, kappa, norm_partials,      \
+                           (const cx<T>*)ycar, ytab, p.n[1], p.n[2]);                                 \
+    else                                                                                              \
+    hipLaunchKernelGGL((k_cn_strided<T, SV, RCV, GV, YV, false>), dim3(blocks), dim3(threads), sm, p.stream, \
                        (cx<T>*)f, L, C, logZB, nseg, tg, kappa, norm_partials, (const cx<T>*)ycar,    \
                        ytab, p.n[1], p.n[2])
 #define DGPE_CN_S(SV)                                  \
