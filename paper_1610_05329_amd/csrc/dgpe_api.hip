@@ -100,7 +100,7 @@ int ilog2(int v) {
 
 // upper bound of the fused z pass's LDS (16-point segments, FP64 carries)
 size_t c2r_step_lds(int Nz, int B, size_t csz) {
-    const int M = Nz / 2, es = B + 1, nseg = (Nz + 15) / 16;
+    const int M = Nz / 2, es = B == 1 ? 1 : B + 1, nseg = (Nz + 15) / 16;
     const size_t fcap = std::max<size_t>((size_t)(M + 1) * es, ((size_t)2 * nseg * B * 16 + csz - 1) / csz);
     return (fcap + (size_t)Nz * es + M + M + 1) * csz + 16 + (size_t)2 * nseg * 16;
 }

@@ -521,6 +521,11 @@ __global__ void k_ukern(T* __restrict__ out, int Nx, int Ny, int Nz, double dkx,
     }
 }
 
+// stride of a line element in an LDS tile of 2^logB lines, element-major:
+// one pad per element spreads the lines over the banks; a single line needs
+// none (consecutive threads take consecutive elements)
+inline int tile_es(int logB) { return logB == 0 ? 1 : (1 << logB) + 1; }
+
 inline size_t sm_r2c(const Plan& p, int es, size_t csz) {
     const int M = p.n[2] / 2;
     return (size_t)(M * es + M + M + 1) * csz;
@@ -551,7 +556,7 @@ int r2c_blocks(const Plan& p) { return p.n[0] * (p.n[1] >> p.lc.logB_z); }
 template <typename T>
 hipError_t launch_r2c_density(const Plan& p, const void* psi, const double* sigma) {
     if (p.fast && fast_r2c<T>(p, psi, sigma)) return hipGetLastError();
-    const int es = (1 << p.lc.logB_z) + 1;
+    const int es = tile_es(p.lc.logB_z);
     const size_t sm = sm_r2c(p, es, sizeof(cx<T>));
     Phys ph{};
     hipLaunchKernelGGL((k_r2c_z<T, SRC_DENSITY>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm,
@@ -567,7 +572,7 @@ hipError_t launch_r2c_adjoint_s(const Plan& p, const void* mu, const void* psin,
                                 double amp, double* partials, int* nblocks) {
     if (p.fast && fast_r2c_adj<T>(p, mu, psin, phin, amp, partials, nblocks)) return hipGetLastError();
     *nblocks = r2c_blocks(p);
-    const int es = (1 << p.lc.logB_z) + 1;
+    const int es = tile_es(p.lc.logB_z);
     const size_t sm = sm_r2c(p, es, sizeof(cx<T>));
     Phys ph{p.dt, p.g, p.gd, amp, 0};
     hipLaunchKernelGGL((k_r2c_z<T, SRC_ADJ_S>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm,
@@ -584,7 +589,7 @@ hipError_t launch_rows(const Plan& p, bool inverse, const double* npart, int nnp
     if (p.fast && fast_rows<T>(p, inverse, npart, nnpart, sigma_out)) return hipGetLastError();
     if (npart) return hipErrorInvalidValue;  // only the compiled pass reduces the norm
     const int L = p.n[1];
-    const int es = (1 << p.lc.logB_y) + 1;
+    const int es = tile_es(p.lc.logB_y);
     const int nrows = (p.n[2] / 2 + 1) * p.n[0];
     const int blocks = (nrows + (1 << p.lc.logB_y) - 1) >> p.lc.logB_y;
     const size_t sm = (size_t)(L * es + L) * sizeof(cx<T>);
@@ -603,7 +608,7 @@ hipError_t launch_rows(const Plan& p, bool inverse, const double* npart, int nnp
 template <typename T>
 hipError_t launch_xmul(const Plan& p) {
     if (p.fast && fast_xmul<T>(p)) return hipGetLastError();
-    const int es = (1 << p.lc.logB_x) + 1;
+    const int es = tile_es(p.lc.logB_x);
     const int blocks = (p.n[2] / 2 + 1) * (p.n[1] >> p.lc.logB_x);
     const size_t sm = (size_t)(p.n[0] * es + p.n[0]) * sizeof(cx<T>);
     hipLaunchKernelGGL((k_xmul<T>), dim3(blocks), dim3(p.lc.threads), sm, p.stream, (cx<T>*)p.spec,
@@ -619,7 +624,7 @@ hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, con
         return hipGetLastError();
     // only the compiled fused pass starts the y solve or scales Phi by sigma
     if (ycar || phi_sigma) return hipErrorInvalidValue;
-    const int es = (1 << p.lc.logB_z) + 1;
+    const int es = tile_es(p.lc.logB_z);
     const size_t sm = sm_c2r_step(p, es, sizeof(cx<T>));
     const cx_coef k = cn_kappa(p, 2, false);
     const cx<double> kappa = {k.re, k.im};
@@ -652,7 +657,7 @@ hipError_t launch_c2r_step(const Plan& p, const void* psi_in, void* psi_out, con
 template <typename T>
 hipError_t launch_c2r_phi(const Plan& p, void* phi_out) {
     if (p.fast && fast_c2r_phi<T>(p, phi_out)) return hipGetLastError();
-    const int es = (1 << p.lc.logB_z) + 1;
+    const int es = tile_es(p.lc.logB_z);
     const size_t sm = sm_c2r_phi(p, es, sizeof(cx<T>));
     hipLaunchKernelGGL((k_c2r_phi<T>), dim3(r2c_blocks(p)), dim3(p.lc.threads), sm, p.stream,
                        (T*)phi_out, (const cx<T>*)p.spec, p.n[0], p.n[1], p.n[2], p.lc.logB_z, es,
