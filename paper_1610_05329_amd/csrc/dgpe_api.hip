@@ -665,16 +665,21 @@ dgpe_status adjoint_impl(Plan& p, const void* psi0, int nsteps, const double* am
         DGPE_HIP(launch_overlap_seed<T>(p, lam, target, coef));
     }
     // one reverse step: the conjugate sweeps, the adjoint source and its
-    // convolution, the nonlinear adjoint update; source sums into partial set i
+    // convolution, the nonlinear adjoint update; source sums into partial set i.
+    // The reverse steps run n = nsteps - 1 down to 0 on lam, recomputation
+    // between them touching other buffers; the compiled update of step n > 0
+    // also applies the conjugate z sweep that opens step n - 1 (zpre).
+    bool zpre = false;
     auto reverse_step = [&](int n, const void* psin, const void* phin, int i) -> dgpe_status {
-        DGPE_HIP(launch_cn_z<T>(p, lam, true));
+        if (!zpre) DGPE_HIP(launch_cn_z<T>(p, lam, true));
         DGPE_HIP(launch_cn_strided<T>(p, lam, 1, true, nullptr));
         DGPE_HIP(launch_cn_strided<T>(p, lam, 0, true, nullptr));
         DGPE_HIP(launch_r2c_adjoint_s<T>(p, lam, psin, phin, amp[n], part + set_stride * i, &nbs));
         DGPE_HIP(launch_rows<T>(p, false));
         DGPE_HIP(launch_xmul<T>(p));
         DGPE_HIP(launch_rows<T>(p, true));
-        if (!(p.fast && fast_c2r_adjupd<T>(p, lam, psin, phin, amp[n]))) {
+        zpre = false;
+        if (!(p.fast && fast_c2r_adjupd<T>(p, lam, psin, phin, amp[n], n > 0, &zpre))) {
             DGPE_HIP(launch_c2r_phi<T>(p, phis));
             DGPE_HIP(launch_adj_update<T>(p, lam, psin, phin, phis, amp[n]));
         }

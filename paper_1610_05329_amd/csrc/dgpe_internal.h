@@ -181,7 +181,10 @@ bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* p
                   double* partials, int* nblocks);
 // fused C2R of Phi_s + adjoint nonlinear update (false: no compiled split)
 template <typename T>
-bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp);
+// zsweep: also apply the conjugate z sweep of the next reverse step where the
+// fused form exists; *zdone tells whether it ran
+bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp,
+                     bool zsweep, bool* zdone);
 template <typename T>
 bool fast_c2r_phi(const Plan& p, void* phi);
 // the C2R of Phi fused with the pointwise half step of the symmetric scheme

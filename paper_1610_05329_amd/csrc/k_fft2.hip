@@ -539,11 +539,27 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 // and w = dt (g s + g_d Phi_s),  lam <- e^{+i theta} mu + 2 w psi_n  (lam holds
 // mu on entry).  Phi_s stays in LDS; the pointwise update runs over the
 // block's NB lines in coalesced 16-byte units.
+//
+// ZF: the update is followed by the conjugate z sweep that opens the next
+// reverse step (the sweeps commute, so it may come first there): each wave
+// then holds LPW whole lines in the fused z pass's layout, transposes its
+// updated values through its own Phi_s rows to the segment layout and solves
+// as the fused z pass does (conjugate tables cntab, kappa64).  The result is
+// the one of this kernel followed by the standalone z sweep, bit for bit.
 template <typename T, int R1, int R2>
+constexpr bool adjupd_zf_ok() {  // whole 16-point segments on whole waves
+    constexpr int M = R1 * R2, Nz = 2 * M, nseg = Nz / 16;
+    constexpr int NB = rows_per_block<T, R1, M>();
+    return Nz % 16 == 0 && nseg <= 16 && (nseg & (nseg - 1)) == 0 &&
+           (NB * R1 / 64) * (64 / nseg) == NB && 2 * R2 == 16;
+}
+
+template <typename T, int R1, int R2, bool ZF>
 __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     k_c2r_adjupd2(cx<T>* __restrict__ lam, const cx<T>* __restrict__ psin,
                   const T* __restrict__ phin, const cx<T>* __restrict__ spec, int Nx, int Ny,
-                  const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c, Phys2 ph) {
+                  const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c, Phys2 ph,
+                  const cx<double>* __restrict__ cntab, cx<double> kappa64) {
     constexpr int M = R1 * R2;
     constexpr int Nz = 2 * M;
     constexpr int NB = rows_per_block<T, R1, M>();
@@ -552,10 +568,24 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     constexpr int U = 16 / (int)sizeof(cx<T>);
     constexpr int NU = NB * Nz / (NT * U);
     static_assert(NU * NT * U == NB * Nz, "whole units");
+    static_assert(!ZF || adjupd_zf_ok<T, R1, R2>(), "z sweep on whole waves of whole lines");
     constexpr int REG = c2r_region<R1, R2, NB>() > NB * PS ? c2r_region<R1, R2, NB>() : NB * PS;
-    __shared__ cx<T> reg[REG];
+    // ZF geometry: the fused z pass's (16-point segments, LPW lines per wave)
+    using A = cn_acc_t<T, false>;
+    constexpr int SZ = 16, nseg = Nz / SZ;
+    constexpr int LPW = ZF ? 64 / nseg : 1;
+    constexpr int SL = Nz + nseg * U;
+    constexpr int fit = (LPW * PS) / SL;
+    constexpr int KR = fit >= LPW ? LPW : fit >= 8 ? 8 : fit >= 4 ? 4 : fit >= 2 ? 2 : 1;
+    constexpr int TS = ZF ? Nz + Nz / SZ : 1;
+    __shared__ __align__(16) cx<T> reg[REG];
     __shared__ cx<T> stw[M];
     __shared__ cx<T> sr2c[M + 1];
+    __shared__ cx<A> ta[TS];
+    __shared__ cx<A> tp[TS];
+    __shared__ cx<A> tq[TS];
+    __shared__ cx<A> spe[ZF ? nseg : 1];
+    __shared__ cx<A> sqb[ZF ? nseg : 1];
     const int tid = threadIdx.x;
     const int ngy = Ny / NB;
     const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -565,11 +595,29 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     TabRegs<cx<T>, M, NT> rtw;
     TabRegs<cx<T>, M + 1, NT> rr2;
     SpecRegs<T, M, NB, NT> rs;
+    TabRegs<cx<double>, ZF ? Nz : 1, NT> rta, rtp, rtq;
+    TabRegs<cx<double>, ZF ? nseg : 1, NT> rpe, rqb;
     tab_issue(rtw, twz, tid);
     tab_issue(rr2, twr2c, tid);
+    if constexpr (ZF) {
+        tab_issue(rta, cntab + TAB_ALPHA * Nz, tid);
+        tab_issue(rtp, cntab + TAB_P * Nz, tid);
+        tab_issue(rtq, cntab + TAB_Q * Nz, tid);
+        tab_issue(rpe, cntab + TAB_PEND * Nz, tid);
+        tab_issue(rqb, cntab + TAB_QBEG * Nz, tid);
+    }
     c2r_issue_loads(rs, spec, (size_t)Nx * Ny, line0, tid);
     tab_stage(rtw, stw, tid, [](int i) { return i; });
     tab_stage(rr2, sr2c, tid, [](int i) { return i; });
+    if constexpr (ZF) {
+        const auto ident = [](int i) { return i; };
+        const auto padded = [](int i) { return i + i / SZ; };
+        tab_stage(rta, ta, tid, padded);
+        tab_stage(rtp, tp, tid, padded);
+        tab_stage(rtq, tq, tid, padded);
+        tab_stage(rpe, spe, tid, ident);
+        tab_stage(rqb, sqb, tid, ident);
+    }
     c2r_stage(rs, reg, tid);
     __syncthreads();
     cx<T> w[R1];
@@ -590,23 +638,28 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
     const T dt = T(ph.dt), gg = T(ph.g), gdd = T(ph.gd), amp = T(ph.amp);
     const T xx = T(x - ph.hx) * T(ph.dx);
     const T vx = T(ph.cx) * xx * xx;
+    // value j of this thread: element (line b, z e) of the block's lines.
+    // ZF: the wave's LPW lines, unit j of the lane at (j * 64 + lane) U of
+    // them; otherwise unit i of the block at (i NT + tid) U.
+    const int lane = tid & 63, wv = tid >> 6;
+    const auto elem = [&](int j) { return ZF ? wv * LPW * Nz + (j * 64 + lane) * U : (j * NT + tid) * U; };
     cx<T> mu[NU * U], pn[NU * U];
     T fn[NU * U];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
-        const int e = (i * NT + tid) * U;
+        const int e = elem(i);
         load_unit<T>(lam + base + e, mu + i * U);
         load_unit<T>(psin + base + e, pn + i * U);
 #pragma unroll
         for (int u = 0; u < U; ++u) fn[i * U + u] = phin[base + e + u];
     }
+    cx<T> o[NU * U];
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
-        const int e = (i * NT + tid) * U;
+        const int e = elem(i);
         const int b = e / Nz;
         const T yy = T(y0 + b - ph.hy) * T(ph.dy);
         const T vxy = vx + T(ph.cy) * yy * yy;
-        cx<T> o[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int iz = e % Nz + u;
@@ -621,10 +674,24 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
             sin_cos(th, &sn, &cs);
             const cx<T> pp = {p.x * cs + p.y * sn, p.y * cs - p.x * sn};
             const T sv = m.x * pp.y - m.y * pp.x;
-            const T wv = dt * (gg * sv + gdd * phis);
-            o[u] = cx<T>{m.x * cs - m.y * sn + T(2) * wv * p.x, m.y * cs + m.x * sn + T(2) * wv * p.y};
+            const T wv2 = dt * (gg * sv + gdd * phis);
+            o[i * U + u] = cx<T>{m.x * cs - m.y * sn + T(2) * wv2 * p.x,
+                                 m.y * cs + m.x * sn + T(2) * wv2 * p.y};
         }
-        store_unit<T>(lam + base + e, o);
+        if constexpr (!ZF) store_unit<T>(lam + base + e, o + i * U);
+    }
+    if constexpr (ZF) {
+        static_assert(NU * U == SZ, "a lane's units are one segment's worth of values");
+        using WL = WaveLines<T, Nz, SZ, KR>;
+        // this wave's Phi_s rows are read: they stage the transposes
+        cx<T>* stg = reg + wv * LPW * PS;
+        const int seg = lane % nseg;
+        cx<A> v[SZ];
+        WL::to_segments(stg, o, v, lane);
+        const cx<A> kappa = {A(kappa64.x), A(kappa64.y)};
+        const int tb = seg * (SZ + 1);
+        cn_segment_solve_wave<T, SZ, nseg, false>(v, kappa, ta + tb, tp + tb, tq + tb, spe, sqb, seg);
+        WL::store_from_segments(stg, v, lam + base + wv * LPW * Nz, lane);
     }
 }
 
@@ -1170,7 +1237,9 @@ bool fast_r2c_adj(const Plan& p, const void* mu, const void* psin, const void* p
 }
 
 template <typename T>
-bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp) {
+bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phin, double amp,
+                     bool zsweep, bool* zdone) {
+    *zdone = false;
     const int M = p.n[2] / 2;
     const Split2 s = fast_split(M);
     if (!s.r1) return false;
@@ -1180,15 +1249,31 @@ bool fast_c2r_adjupd(const Plan& p, void* lam, const void* psin, const void* phi
     Phys2 ph{p.dt, p.g, p.gd, amp, 0, p.n[0] / 2, p.n[1] / 2, p.n[2] / 2,
              p.d[0], p.d[1], p.d[2], 0.5 * p.trap[0] * p.trap[0], 0.5 * p.trap[1] * p.trap[1],
              0.5 * p.trap[2] * p.trap[2]};
+    // the conjugate z sweep of the next reverse step, where the z tables hold
+    // 16-point segments and the split has the fused form
+    const bool zf = zsweep && !p.imag && p.lc.seg[2] == 16;
+    const cx<double>* ztab = (const cx<double>*)p.cntab[2][1];
+    const cx_coef kz = cn_kappa(p, 2, true);
+    const cx<double> kappa = {kz.re, kz.im};
     switch (M) {
+#define DGPE_LAUNCH(A, B, ZFV)                                                                       \
+    hipLaunchKernelGGL((k_c2r_adjupd2<T, A, B, ZFV>), dim3(blocks), dim3(nb * A), 0, p.stream,       \
+                       (cx<T>*)lam, (const cx<T>*)psin, (const T*)phin, (const cx<T>*)p.spec,        \
+                       p.n[0], p.n[1], (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, ph, ztab, kappa)
 #define DGPE_CASE(A, B)                                                                              \
     case A * B:                                                                                      \
-        hipLaunchKernelGGL((k_c2r_adjupd2<T, A, B>), dim3(blocks), dim3(nb * A), 0, p.stream,        \
-                           (cx<T>*)lam, (const cx<T>*)psin, (const T*)phin, (const cx<T>*)p.spec,    \
-                           p.n[0], p.n[1], (const cx<T>*)p.tw[2], (const cx<T>*)p.twr2c, ph);        \
+        if constexpr (adjupd_zf_ok<T, A, B>()) {                                                     \
+            if (zf) {                                                                                \
+                DGPE_LAUNCH(A, B, true);                                                             \
+                *zdone = true;                                                                       \
+                return true;                                                                         \
+            }                                                                                        \
+        }                                                                                            \
+        DGPE_LAUNCH(A, B, false);                                                                    \
         return true;
         DGPE_SPLITS(DGPE_CASE)
 #undef DGPE_CASE
+#undef DGPE_LAUNCH
         default: return false;
     }
 }
@@ -1326,7 +1411,8 @@ bool fast_c2r_step(const Plan& p, const void* psi_in, void* psi_out, const doubl
                                   double*, int*);                   \
     template bool fast_c2r_phi<T>(const Plan&, void*);               \
     template bool fast_c2r_nl<T>(const Plan&, void*, double, double, double*, int*); \
-    template bool fast_c2r_adjupd<T>(const Plan&, void*, const void*, const void*, double); \
+    template bool fast_c2r_adjupd<T>(const Plan&, void*, const void*, const void*, double, bool, \
+                                     bool*);                                                      \
     template bool fast_c2r_step<T>(const Plan&, const void*, void*, const double*, double, void*, \
                                    void*, bool);                                                  \
     template bool fast_rows_sigma_ok<T>(const Plan&);                                             \
