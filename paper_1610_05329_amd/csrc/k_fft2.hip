@@ -544,8 +544,8 @@ __global__ void __launch_bounds__((rows_per_block<T, R1, R1 * R2>() * R1))
 // reverse step (the sweeps commute, so it may come first there): each wave
 // then holds LPW whole lines in the fused z pass's layout, transposes its
 // updated values through its own Phi_s rows to the segment layout and solves
-// as the fused z pass does (conjugate tables cntab, kappa64).  The result is
-// the one of this kernel followed by the standalone z sweep, bit for bit.
+// as the fused z pass does (conjugate tables cntab, kappa64): the arithmetic
+// of this kernel followed by the standalone z sweep.
 template <typename T, int R1, int R2>
 constexpr bool adjupd_zf_ok() {  // whole 16-point segments on whole waves
     constexpr int M = R1 * R2, Nz = 2 * M, nseg = Nz / 16;
