@@ -866,9 +866,13 @@ struct Step2Geom {
 // [Nx][Ny/16][Nz] to ycar: d at the last line plus u there, x at the first
 // line plus u there, and u at the first line; the carry pass turns these into
 // c_d and c_x, which the x sweep adds while it loads.
+//
+// Occupancy: FP32 imaginary time at five waves per SIMD; the FP64 fused-y
+// variant at 256-point lines at three (168 registers, a few spilled: 147 ->
+// 142 us at 256^3 against two waves at its natural 180).
 template <typename T, int R1, int R2, int SZ, bool RC, bool PHI, bool YF>
 __global__ void __launch_bounds__((step2_threads<T, R1, R2, SZ>()))
-__attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : 1, 8)))
+__attribute__((amdgpu_waves_per_eu(RC && sizeof(T) == 4 ? 5 : (YF && R1 * R2 == 128 ? 3 : 1), 8)))
     k_c2r_step2(const cx<T>* psi_in, cx<T>* psi_out, T* __restrict__ phi_out,
                 const cx<T>* __restrict__ spec, int Nx, int Ny,
                 const cx<T>* __restrict__ twz, const cx<T>* __restrict__ twr2c,
