@@ -146,6 +146,28 @@ def test_adjoint_independent_of_checkpoint_interval(env):
         assert torch.equal(out["dJ_dpsi0"], ref["dJ_dpsi0"])
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_with_compiled_passes_independent_of_checkpoint_interval(env, prec):
+    """With the compiled z passes (z lines of 128 points: the recompute steps'
+    fused z pass that keeps Phi, the adjoint-source R2C, and the nonlinear
+    adjoint update that also applies the next reverse step's conjugate z
+    sweep) the gradients do not depend on the checkpoint interval, bit for
+    bit."""
+    torch, dg = env
+    n, d = (6, 32, 128), (0.5, 0.3, 0.1)
+    psi0 = W.random_state(n, d, seed=71)
+    amp = np.random.default_rng(72).uniform(0.8, 1.2, size=9)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    plan = dg.Plan(n, d, 0.004, (1.0, 1.3, 1.1), 12.0, 7.0, real_time=True, dtype=dt)
+    ref = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=4)
+    for k in (1, 3, 100):
+        out = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=k)
+        assert out["J"] == ref["J"]
+        assert np.array_equal(out["dJ_damp"], ref["dJ_damp"])
+        assert torch.equal(out["dJ_dpsi0"], ref["dJ_dpsi0"])
+    plan.close()
+
+
 def test_potential_is_linear_and_symmetric(env):
     """Phi is linear in the density and the discrete convolution is symmetric:
     sum n1 Phi[n2] = sum n2 Phi[n1] (real even kernel)."""
