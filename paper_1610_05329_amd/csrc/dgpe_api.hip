@@ -885,6 +885,52 @@ dgpe_status scratch_for_device(int dev, void** out) {
 // C ABI
 // ============================================================================
 
+// A fixed sequence of launches on the plan's stream, captured as a HIP graph
+// on its first run and replayed afterwards (plain launches if capture is not
+// possible).  The capture runs on a private stream that stands in for the
+// plan's (the legacy default stream cannot be captured); the replays go to the
+// plan's stream, in order with its other work.  The sequence must record no
+// memset and call nothing that synchronises.  Plans that must not allocate
+// (static workspace) keep plain launches: instantiating a graph allocates.
+struct ChunkGraph {
+    Plan& p;
+    hipStream_t cs = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool eager = false;
+    explicit ChunkGraph(Plan& plan) : p(plan), eager(plan.static_ws) {}
+    ~ChunkGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+    template <typename F>
+    dgpe_status run(F launches) {
+        if (!exec && !eager) {
+            eager = true;  // unless everything below succeeds
+            hipGraph_t g = nullptr;
+            if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+                hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                const hipStream_t own = p.stream;
+                p.stream = cs;
+                const dgpe_status st = launches();
+                p.stream = own;
+                const hipError_t e = hipStreamEndCapture(cs, &g);
+                if (st == DGPE_OK && e == hipSuccess && g &&
+                    hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
+                    eager = false;
+                else
+                    exec = nullptr;
+            }
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+        }
+        if (exec) {
+            DGPE_HIP(hipGraphLaunch(exec, p.stream));
+            return DGPE_OK;
+        }
+        return launches();
+    }
+};
+
 extern "C" {
 
 const char* dgpe_status_string(dgpe_status s) {
@@ -1052,9 +1098,18 @@ dgpe_status dgpe_ground_state(dgpe_plan plan, void* psi, double tol, int32_t max
     if ((st = obs_of(&o)) != DGPE_OK) return st;
     double mu = o.mu, rate = INFINITY;
     int done = 0;
+    auto steps = [&](int k) {
+        return p.f32 ? run_steps<float>(p, psi, k, nullptr) : run_steps<double>(p, psi, k, nullptr);
+    };
+    // The check_every steps between two checks are the same launches every
+    // time (same buffers and parameters): captured once as a HIP graph and
+    // replayed, they reach the GPU without one host launch per kernel.  If
+    // the capture fails the steps run as plain launches.
+    ChunkGraph chunk(p);
     while (done < max_steps) {
         const int k = std::min(check_every, max_steps - done);
-        st = p.f32 ? run_steps<float>(p, psi, k, nullptr) : run_steps<double>(p, psi, k, nullptr);
+        if (k == check_every) st = chunk.run([&] { return steps(k); });
+        else st = steps(k);
         if (st != DGPE_OK) return st;
         done += k;
         if ((st = obs_of(&o)) != DGPE_OK) return st;

@@ -147,6 +147,31 @@ def test_ground_state_driver_matches_oracle(env, prec, scheme):
     plan.close()
 
 
+@pytest.mark.parametrize("scheme", ["lie", "strang"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_ground_state_driver_graph_replays_match_plain_steps(env, prec, scheme):
+    """The driver captures its check_every steps as a HIP graph on the first
+    chunk and replays it for the next ones, with the observables (eager work
+    that synchronises) between replays: after 1 to 4 chunks the state equals
+    the same number of plain step calls, bit for bit."""
+    torch, dg = env
+    n, d = (16, 32, 64), (0.5, 0.4, 0.3)
+    cfg = W.Config("t", n, d, 0.01, (1.0, 1.3, 1.7), 15.0, 6.0, True, 0, noise=1e-3, seed=35)
+    psi0 = W.noisy_gaussian(cfg)
+    every = 5
+    plan = dg.Plan(n, d, cfg.dt, cfg.trap, cfg.g, cfg.gd, dtype=_dtype(torch, prec))
+    plan.set("scheme", scheme)
+    for chunks in (1, 2, 3, 4):
+        psi = plan.new_state(psi0)
+        out = plan.ground_state(psi, tol=1e-300, max_steps=chunks * every, check_every=every)
+        assert out["steps"] == chunks * every and not out["converged"]
+        ref = plan.new_state(psi0)
+        for _ in range(chunks):
+            plan.step(ref, every)
+        assert torch.equal(psi, ref), f"{chunks} chunks"
+    plan.close()
+
+
 def test_ground_state_driver_arguments(env):
     torch, dg = env
     n, d = (16, 24, 32), (0.4, 0.35, 0.3)
