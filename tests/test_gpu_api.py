@@ -147,6 +147,27 @@ def test_adjoint_independent_of_checkpoint_interval(env):
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_adjoint_long_x_lines_matches_oracle(env, prec):
+    """x lines of 2048 points: the forward and the conjugate x sweeps read their
+    Thomas tables from global memory (tables of 128 segments would crowd the
+    LDS); energy objective against the oracle."""
+    torch, dg = env
+    n, d = (2048, 4, 16), (0.02, 0.6, 0.4)
+    p = O.Params(n, d, 0.004, (1.0, 1.3, 1.1), 12.0, 7.0, False)
+    psi0 = W.random_state(n, d, seed=91)
+    amp = np.random.default_rng(92).uniform(0.8, 1.2, size=5)
+    J, psiN, dJ_da, dJ_dt, lam0 = O.adjoint_evolve(p, psi0, amp, "energy", None)
+    dt = torch.complex128 if prec == "f64" else torch.complex64
+    plan = dg.Plan(n, d, p.dt, p.trap, p.g, p.gd, real_time=True, dtype=dt)
+    out = plan.adjoint(plan.new_state(psi0), amp, ckpt_every=2)
+    errs = _adjoint_errors(out, J, dJ_da, dJ_dt, lam0)
+    print(f"  adjoint 2048-point x lines {prec}: J {errs[0]:.2e} dJ/da {errs[1]:.2e} "
+          f"dJ/dtrap {errs[2]:.2e} lam0 {errs[3]:.2e}", flush=True)
+    assert max(errs) < (1e-10 if prec == "f64" else 5e-5)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_adjoint_with_compiled_passes_independent_of_checkpoint_interval(env, prec):
     """With the compiled z passes (z lines of 128 points: the recompute steps'
     fused z pass that keeps Phi, the adjoint-source R2C, and the nonlinear
